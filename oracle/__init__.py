@@ -1,0 +1,194 @@
+"""Plain FP64 CPU oracle for the explicit level-set time step of arXiv 2507.11542.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product path never imports
+this package, and this package imports nothing from the product.
+
+The arithmetic lives in ``hj_oracle.c`` (plain scalar loops, FP64); this module
+only marshals numpy arrays through ctypes.  ``build()`` compiles it with gcc.
+Functions and the paper passages they follow:
+
+- ``schedule``  alpha, CFL dt and step count          (Sec. 4 CFL condition, Sec. 5 time loop)
+- ``derivs``    one-sided derivatives along one axis   (Sec. 3, 3.1, 3.2, 3.3)
+- ``rhs_at``    L(V) = -Hhat at chosen nodes          (Sec. 4 Lax-Friedrichs)
+- ``steps``     fixed-size TVD-RK steps               (Sec. 5 odeCFL listing)
+- ``solve``     full CFL-constrained solve over tspan (Sec. 5, Sec. 6.1 tube)
+
+Every function is pinned by a ``-m "not gpu"`` test against closed forms,
+invariants, polynomial reproduction, convergence order or brute force; the
+values of the relative-Dubins and 4-D Dubins solves away from the front are
+"parity unpinned" (no closed form exists; the pins constrain them only through
+the shared operators and symmetries).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hj_oracle.c")
+_LIB = os.path.join(_HERE, "libhj_oracle.so")
+# a test may point the shim at a deliberately mutated build of the oracle
+_LIB = os.environ.get("HJ_ORACLE_LIB", _LIB)
+
+SCHEMES = {"upwind1": 1, "eno2": 2, "weno5": 5}
+DYNAMICS = {"translation": 0, "ball": 1, "double_integrator": 2,
+            "rel_dubins": 3, "dubins4d": 4}
+MODES = {"set": 0, "tube": 1}
+
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle with gcc (IEEE FP64, no contraction, OpenMP loops)."""
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-std=c99", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    L = ctypes.c_long
+    D = ctypes.c_double
+    U = ctypes.c_uint
+    lib.orc_schedule.argtypes = [I, P, P, P, U, I, P, I, D, D, D, P, P, P, P]
+    lib.orc_schedule.restype = I
+    lib.orc_derivs.argtypes = [I, P, P, P, U, I, I, P, P, P]
+    lib.orc_derivs.restype = I
+    lib.orc_rhs_at.argtypes = [I, P, P, P, U, I, P, I, I, P, P, L, P, P]
+    lib.orc_rhs_at.restype = I
+    lib.orc_steps.argtypes = [I, P, P, P, U, I, P, I, I, I, P, D, L, P, P, I]
+    lib.orc_steps.restype = I
+    lib.orc_solve.argtypes = [I, P, P, P, U, I, P, I, I, I, D, P, P, D, D, I, P, P]
+    lib.orc_solve.restype = L
+    lib.orc_set_threads.argtypes = [I]
+    lib.orc_set_threads.restype = I
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _grid_args(n, lo, hi, periodic):
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    mask = 0
+    for d, p in enumerate(periodic):
+        if p:
+            mask |= 1 << d
+    return n, lo, hi, mask
+
+
+def _params(params):
+    p = np.zeros(8, dtype=np.float64)
+    params = list(params)
+    p[: len(params)] = params
+    return p, len(params)
+
+
+def set_threads(n: int = 0) -> int:
+    """Host threads for the node loops (0: all); returns the count in use."""
+    return int(_load().orc_set_threads(int(n)))
+
+
+def schedule(n, lo, hi, periodic, dynamics, params, cfl, t0, tf):
+    """alpha per axis, dt, step count and final time of a solve (Sec. 4, Sec. 5)."""
+    lib = _load()
+    n, lo, hi, mask = _grid_args(n, lo, hi, periodic)
+    p, npar = _params(params)
+    alpha = np.zeros(4)
+    dt = np.zeros(1)
+    steps = np.zeros(1, dtype=np.int64)
+    tend = np.zeros(1)
+    rc = lib.orc_schedule(len(n), _ptr(n), _ptr(lo), _ptr(hi), mask,
+                          DYNAMICS[dynamics], _ptr(p), npar, float(cfl), float(t0),
+                          float(tf), _ptr(alpha), _ptr(dt), _ptr(steps), _ptr(tend))
+    if rc != 0:
+        raise ValueError("oracle schedule: bad grid")
+    return alpha[: len(n)].copy(), float(dt[0]), int(steps[0]), float(tend[0])
+
+
+def derivs(v, n, lo, hi, periodic, scheme, axis):
+    """(p-, p+) along `axis` at every node (Sec. 3)."""
+    lib = _load()
+    n, lo, hi, mask = _grid_args(n, lo, hi, periodic)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    assert v.size == int(np.prod(n))
+    pm = np.empty_like(v)
+    pp = np.empty_like(v)
+    rc = lib.orc_derivs(len(n), _ptr(n), _ptr(lo), _ptr(hi), mask, SCHEMES[scheme],
+                        int(axis), _ptr(v), _ptr(pm), _ptr(pp))
+    if rc != 0:
+        raise ValueError("oracle derivs: bad grid")
+    return pm, pp
+
+
+def rhs_at(v, n, lo, hi, periodic, dynamics, params, scheme, alpha, nodes):
+    """L(V) = -Hhat at the flat node indices `nodes` (Sec. 4)."""
+    lib = _load()
+    n, lo, hi, mask = _grid_args(n, lo, hi, periodic)
+    p, npar = _params(params)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    a = np.zeros(4)
+    a[: len(n)] = alpha
+    out = np.empty(nodes.size)
+    rc = lib.orc_rhs_at(len(n), _ptr(n), _ptr(lo), _ptr(hi), mask, DYNAMICS[dynamics],
+                        _ptr(p), npar, SCHEMES[scheme], _ptr(a), _ptr(v), nodes.size,
+                        _ptr(nodes), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle rhs_at: bad grid")
+    return out
+
+
+def steps(v, v0, n, lo, hi, periodic, dynamics, params, scheme, order, alpha, h,
+          nsteps, mode="set"):
+    """`nsteps` TVD-RK steps of size h from v (returns a new array; Sec. 5)."""
+    lib = _load()
+    n, lo, hi, mask = _grid_args(n, lo, hi, periodic)
+    p, npar = _params(params)
+    out = np.array(v, dtype=np.float64, order="C", copy=True)
+    v0 = np.ascontiguousarray(v0 if v0 is not None else v, dtype=np.float64)
+    a = np.zeros(4)
+    a[: len(n)] = alpha
+    rc = lib.orc_steps(len(n), _ptr(n), _ptr(lo), _ptr(hi), mask, DYNAMICS[dynamics],
+                       _ptr(p), npar, SCHEMES[scheme], int(order), _ptr(a), float(h),
+                       int(nsteps), _ptr(out), _ptr(v0), MODES[mode])
+    if rc != 0:
+        raise RuntimeError("oracle steps failed")
+    return out
+
+
+def solve(v0, n, lo, hi, periodic, dynamics, params, scheme="weno5", order=3,
+          cfl=0.8, t0=0.0, tf=1.0, mode="set"):
+    """Full solve over [t0, tf]; returns (V(tf), alpha, dt, steps) (Sec. 5)."""
+    lib = _load()
+    n, lo, hi, mask = _grid_args(n, lo, hi, periodic)
+    p, npar = _params(params)
+    v0 = np.ascontiguousarray(v0, dtype=np.float64)
+    assert v0.size == int(np.prod(n))
+    out = np.empty_like(v0)
+    alpha = np.zeros(4)
+    dt = np.zeros(1)
+    k = lib.orc_solve(len(n), _ptr(n), _ptr(lo), _ptr(hi), mask, DYNAMICS[dynamics],
+                      _ptr(p), npar, SCHEMES[scheme], int(order), float(cfl), _ptr(v0),
+                      _ptr(out), float(t0), float(tf), MODES[mode], _ptr(alpha), _ptr(dt))
+    if k < 0:
+        raise RuntimeError("oracle solve failed (%d)" % k)
+    return out, alpha[: len(n)].copy(), float(dt[0]), int(k)

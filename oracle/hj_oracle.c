@@ -1,0 +1,577 @@
+/*
+ * hj_oracle.c -- plain FP64 CPU reference solver for the explicit level-set
+ * time step of arXiv 2507.11542 (LevelSetPy).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant with the GPU library: every formula below is
+ * written out again from the paper (and, where the paper defers to it, from
+ * Osher & Fedkiw, "Level Set Methods and Dynamic Implicit Surfaces").
+ *
+ * What it computes (paper section in brackets):
+ *   - grid nodes and ghost values                        [Sec. 2.1, Fig. 3]
+ *   - one-sided derivatives p-/p+ per axis:
+ *       first order upwind                               [Sec. 3, eq. (fwd_bck_differencing), Sec. 3.1]
+ *       ENO2 from the divided-difference table           [Sec. 3.2]
+ *       WENO5 (Jiang-Peng weights)                       [Sec. 3.3]
+ *   - Lax-Friedrichs numerical Hamiltonian               [Sec. 4, LF equation]
+ *   - dissipation alpha_i = max over nodes of |dH/dp_i| bound, CFL dt [Sec. 4]
+ *   - TVD Runge-Kutta 1/2/3 and the CFL time loop        [Sec. 5, odeCFL3 listing]
+ *   - tube update V <- min(V, V0) after each step        [Sec. 6.1 BRT]
+ *
+ * Readings where the paper is silent or garbled (all are also listed in the
+ * design notes):
+ *   R1  D- v_i = (v_i - v_{i-1})/dx, D+ v_i = (v_{i+1} - v_i)/dx; the printed
+ *       difference equation has the labels swapped, the upwind rule of Sec. 3.1
+ *       (use D- when the speed is positive) fixes the direction.
+ *   R2  ENO2: D1_{k+1/2} = (v_{k+1}-v_k)/dx, D2_k = (D1_{k+1/2}-D1_{k-1/2})/(2dx);
+ *       p- = D1_{i-1/2} + dx*m(D2_{i-1}, D2_i), p+ = D1_{i+1/2} - dx*m(D2_i, D2_{i+1}),
+ *       m(a,b) = a if |a| <= |b| else b (the <= tie rule printed for ENO3).
+ *   R3  WENO5: Jiang-Peng with eps = 1e-6*max(v_k^2) + 1e-99.
+ *   R4  alpha_i = max over grid nodes of max over controls |f_i(x,u,d)|;
+ *       computed once per solve (it does not depend on V).
+ *   R5  dt = cfl / sum_i alpha_i/dx_i, fixed for all stages of a step.
+ *   R6  loop while (tf - t) >= eps*(tf - t0), eps = 100*2^-52, h = min(dt, tf-t).
+ *   R7  RK2 = Shu-Osher TVD-RK2 (Heun): V1 = V + h L(V); V+ = (V + V1 + h L(V1))/2.
+ *   R8  RK3 as the odeCFL3 listing: V1 = V + hL(V); V2 = V1 + hL(V1);
+ *       Vh = (3V + V2)/4; V3 = Vh + hL(Vh); V+ = (V + 2 V3)/3.
+ *   R9  V_t + H(x, grad V) = 0 integrated forward from V0; H = -opt p.f.
+ *   R11 tube: V <- min(V, V0) after every full step.
+ *   R12 non-periodic ghosts: linear extrapolation v_{-k} = v_0 + k (v_0 - v_1).
+ *   R14 non-periodic axis: dx = (hi-lo)/(N-1), both ends are nodes;
+ *       periodic axis: dx = (hi-lo)/N, hi is not a node.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXD 4
+
+/* scheme, integrator and dynamics codes of this file (the Python shim maps
+ * names to them; nothing outside this file shares them) */
+enum { ORC_UPWIND1 = 1, ORC_ENO2 = 2, ORC_WENO5 = 5 };
+enum { ORC_TRANSLATION = 0, ORC_BALL = 1, ORC_DOUBLE_INTEGRATOR = 2,
+       ORC_REL_DUBINS = 3, ORC_DUBINS4D = 4 };
+enum { ORC_SET = 0, ORC_TUBE = 1 };
+
+typedef struct {
+    int nd;
+    long n[ORC_MAXD];
+    long stride[ORC_MAXD];
+    long total;
+    double lo[ORC_MAXD], hi[ORC_MAXD], dx[ORC_MAXD];
+    int periodic[ORC_MAXD];
+    double *x[ORC_MAXD]; /* node coordinates per axis */
+    double *cs[ORC_MAXD]; /* cos of the node coordinates */
+    double *sn[ORC_MAXD]; /* sin of the node coordinates */
+} ogrid;
+
+typedef struct {
+    int kind;
+    double prm[8];
+} odyn;
+
+/* ---------------------------------------------------------------- grid */
+
+/* Sec. 2.1 (createGrid): nodes lo + k*dx per axis; reading R14 for dx. */
+static int grid_init(ogrid *g, int nd, const long *n, const double *lo,
+                     const double *hi, unsigned periodic_mask)
+{
+    if (nd < 1 || nd > ORC_MAXD) return -1;
+    g->nd = nd;
+    g->total = 1;
+    for (int d = 0; d < nd; ++d) {
+        g->n[d] = n[d];
+        g->lo[d] = lo[d];
+        g->hi[d] = hi[d];
+        g->periodic[d] = (periodic_mask >> d) & 1u;
+        if (n[d] < 2) return -1;
+        g->dx[d] = g->periodic[d] ? (hi[d] - lo[d]) / (double)n[d]
+                                  : (hi[d] - lo[d]) / (double)(n[d] - 1);
+        g->total *= n[d];
+    }
+    /* C order: the last axis is the fastest */
+    long s = 1;
+    for (int d = nd - 1; d >= 0; --d) {
+        g->stride[d] = s;
+        s *= n[d];
+    }
+    for (int d = 0; d < nd; ++d) {
+        g->x[d] = (double *)malloc(sizeof(double) * (size_t)n[d]);
+        g->cs[d] = (double *)malloc(sizeof(double) * (size_t)n[d]);
+        g->sn[d] = (double *)malloc(sizeof(double) * (size_t)n[d]);
+        if (!g->x[d] || !g->cs[d] || !g->sn[d]) return -2;
+        for (long k = 0; k < n[d]; ++k) {
+            g->x[d][k] = lo[d] + (double)k * g->dx[d];
+            g->cs[d][k] = cos(g->x[d][k]);
+            g->sn[d][k] = sin(g->x[d][k]);
+        }
+    }
+    return 0;
+}
+
+static void grid_free(ogrid *g)
+{
+    for (int d = 0; d < ORC_MAXD; ++d) {
+        free(g->x[d]);
+        free(g->cs[d]);
+        free(g->sn[d]);
+    }
+}
+
+static long axis_index(const ogrid *g, long node, int d)
+{
+    return (node / g->stride[d]) % g->n[d];
+}
+
+/* Fig. 3 / reading R12: value at axis-d index j (possibly a ghost index) on
+ * the grid line through `node`. */
+static double line_value(const ogrid *g, const double *v, long node, int d, long j)
+{
+    long n = g->n[d];
+    long base = node - axis_index(g, node, d) * g->stride[d];
+    if (j >= 0 && j < n) return v[base + j * g->stride[d]];
+    if (g->periodic[d]) {
+        long jj = ((j % n) + n) % n;
+        return v[base + jj * g->stride[d]];
+    }
+    if (j < 0) {
+        double v0 = v[base];
+        double v1 = v[base + g->stride[d]];
+        return v0 + (double)(-j) * (v0 - v1);
+    }
+    {
+        double va = v[base + (n - 1) * g->stride[d]];
+        double vb = v[base + (n - 2) * g->stride[d]];
+        return va + (double)(j - (n - 1)) * (va - vb);
+    }
+}
+
+/* ------------------------------------------------- one-sided derivatives */
+
+/* Sec. 3.3, Jiang-Peng WENO5 from five consecutive one-sided differences
+ * (Osher-Fedkiw eqs. 3.28-3.39); reading R3 for eps. */
+static double weno5(double v1, double v2, double v3, double v4, double v5)
+{
+    double phi1 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
+    double phi2 = -v2 / 6.0 + 5.0 * v3 / 6.0 + v4 / 3.0;
+    double phi3 = v3 / 3.0 + 5.0 * v4 / 6.0 - v5 / 6.0;
+
+    double s1 = 13.0 / 12.0 * (v1 - 2.0 * v2 + v3) * (v1 - 2.0 * v2 + v3)
+              + 0.25 * (v1 - 4.0 * v2 + 3.0 * v3) * (v1 - 4.0 * v2 + 3.0 * v3);
+    double s2 = 13.0 / 12.0 * (v2 - 2.0 * v3 + v4) * (v2 - 2.0 * v3 + v4)
+              + 0.25 * (v2 - v4) * (v2 - v4);
+    double s3 = 13.0 / 12.0 * (v3 - 2.0 * v4 + v5) * (v3 - 2.0 * v4 + v5)
+              + 0.25 * (3.0 * v3 - 4.0 * v4 + v5) * (3.0 * v3 - 4.0 * v4 + v5);
+
+    double mx = v1 * v1;
+    if (v2 * v2 > mx) mx = v2 * v2;
+    if (v3 * v3 > mx) mx = v3 * v3;
+    if (v4 * v4 > mx) mx = v4 * v4;
+    if (v5 * v5 > mx) mx = v5 * v5;
+    double eps = 1e-6 * mx + 1e-99;
+
+    double a1 = 0.1 / ((s1 + eps) * (s1 + eps));
+    double a2 = 0.6 / ((s2 + eps) * (s2 + eps));
+    double a3 = 0.3 / ((s3 + eps) * (s3 + eps));
+    double sum = a1 + a2 + a3;
+    double w1 = a1 / sum, w2 = a2 / sum, w3 = a3 / sum;
+    return w1 * phi1 + w2 * phi2 + w3 * phi3;
+}
+
+/* ENO choice of the smaller second difference, tie to the first argument
+ * (reading R2). */
+static double eno_pick(double a, double b)
+{
+    return fabs(a) <= fabs(b) ? a : b;
+}
+
+/* Sec. 3 (upwinding): left (p-) and right (p+) approximations of dV/dx_d at
+ * one node.  The local stencil is patched with ghost values, then the
+ * divided-difference table of that stencil is formed. */
+static void derivs_at(const ogrid *g, const double *v, long node, int d,
+                      int scheme, double *pm, double *pp)
+{
+    long i = axis_index(g, node, d);
+    double dx = g->dx[d];
+    if (scheme == ORC_UPWIND1) {
+        double vm = line_value(g, v, node, d, i - 1);
+        double vc = line_value(g, v, node, d, i);
+        double vp = line_value(g, v, node, d, i + 1);
+        *pm = (vc - vm) / dx;
+        *pp = (vp - vc) / dx;
+        return;
+    }
+    if (scheme == ORC_ENO2) {
+        /* s[0..4] = v_{i-2} .. v_{i+2} */
+        double s[5];
+        for (int k = 0; k < 5; ++k) s[k] = line_value(g, v, node, d, i - 2 + k);
+        /* first divided differences at half points i-3/2 .. i+3/2 */
+        double d1[4];
+        for (int k = 0; k < 4; ++k) d1[k] = (s[k + 1] - s[k]) / dx;
+        /* second divided differences at nodes i-1, i, i+1 */
+        double d2[3];
+        for (int k = 0; k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) / (2.0 * dx);
+        *pm = d1[1] + dx * eno_pick(d2[0], d2[1]);
+        *pp = d1[2] - dx * eno_pick(d2[1], d2[2]);
+        return;
+    }
+    /* WENO5: s[0..6] = v_{i-3} .. v_{i+3}; D1 at half points i-5/2 .. i+5/2 */
+    double s[7];
+    for (int k = 0; k < 7; ++k) s[k] = line_value(g, v, node, d, i - 3 + k);
+    double d1[6];
+    for (int k = 0; k < 6; ++k) d1[k] = (s[k + 1] - s[k]) / dx;
+    /* p-: D-v at i-2..i+2 = D1 at i-5/2..i+3/2 */
+    *pm = weno5(d1[0], d1[1], d1[2], d1[3], d1[4]);
+    /* p+: D+v at i+2..i-2 = D1 at i+5/2..i-3/2 */
+    *pp = weno5(d1[5], d1[4], d1[3], d1[2], d1[1]);
+}
+
+/* ------------------------------------------------------------ dynamics */
+
+/* Hamiltonian H(x, p) with the sign convention of reading R9.
+ *  TRANSLATION  xdot = b               H = -b.p
+ *  BALL         xdot = s u, |u|_2<=1   H = s |p|_2 (s < 0: the set shrinks)
+ *  DOUBLE_INT.  x1dot = x2, x2dot = u, |u|<=umax, control minimises:
+ *               H = -(p1 x2 + min_u p2 u) = -p1 x2 + umax |p2|
+ *  REL_DUBINS   (x, y, psi): xdot = -ve + vp cos psi + we y,
+ *               ydot = vp sin psi - we x, psidot = wp - we; evader (we)
+ *               maximises, pursuer (wp) minimises:
+ *               H = -max_we min_wp p.f
+ *                 = -p1(-ve + vp cos psi) - p2 vp sin psi
+ *                   - wemax |p1 y - p2 x - p3| + wpmax |p3|
+ *  DUBINS4D     (x, y, th, v): xdot = v cos th, ydot = v sin th, thdot = w,
+ *               vdot = a; control minimises:
+ *               H = -p1 v cos th - p2 v sin th + wmax |p3| + amax |p4|
+ */
+static double hamiltonian(const ogrid *g, const odyn *dy, long node, const double *p)
+{
+    switch (dy->kind) {
+    case ORC_TRANSLATION: {
+        double h = 0.0;
+        for (int d = 0; d < g->nd; ++d) h -= dy->prm[d] * p[d];
+        return h;
+    }
+    case ORC_BALL: {
+        double s = 0.0;
+        for (int d = 0; d < g->nd; ++d) s += p[d] * p[d];
+        return dy->prm[0] * sqrt(s);
+    }
+    case ORC_DOUBLE_INTEGRATOR: {
+        double x2 = g->x[1][axis_index(g, node, 1)];
+        return -p[0] * x2 + dy->prm[0] * fabs(p[1]);
+    }
+    case ORC_REL_DUBINS: {
+        double ve = dy->prm[0], vp = dy->prm[1], we = dy->prm[2], wp = dy->prm[3];
+        double x = g->x[0][axis_index(g, node, 0)];
+        double y = g->x[1][axis_index(g, node, 1)];
+        long k = axis_index(g, node, 2);
+        double c = g->cs[2][k], s = g->sn[2][k];
+        return -p[0] * (-ve + vp * c) - p[1] * (vp * s)
+               - we * fabs(p[0] * y - p[1] * x - p[2]) + wp * fabs(p[2]);
+    }
+    case ORC_DUBINS4D: {
+        double wm = dy->prm[0], am = dy->prm[1];
+        long k = axis_index(g, node, 2);
+        double v = g->x[3][axis_index(g, node, 3)];
+        return -p[0] * (v * g->cs[2][k]) - p[1] * (v * g->sn[2][k])
+               + wm * fabs(p[2]) + am * fabs(p[3]);
+    }
+    }
+    return 0.0;
+}
+
+/* Reading R4: bound over the control sets of |f_d(x, u, d)| = |dH/dp_d| at
+ * one node. */
+static double speed_bound(const ogrid *g, const odyn *dy, long node, int d)
+{
+    switch (dy->kind) {
+    case ORC_TRANSLATION:
+        return fabs(dy->prm[d]);
+    case ORC_BALL:
+        return fabs(dy->prm[0]);
+    case ORC_DOUBLE_INTEGRATOR:
+        if (d == 0) return fabs(g->x[1][axis_index(g, node, 1)]);
+        return dy->prm[0];
+    case ORC_REL_DUBINS: {
+        double ve = dy->prm[0], vp = dy->prm[1], we = dy->prm[2], wp = dy->prm[3];
+        double x = g->x[0][axis_index(g, node, 0)];
+        double y = g->x[1][axis_index(g, node, 1)];
+        long k = axis_index(g, node, 2);
+        if (d == 0) return fabs(-ve + vp * g->cs[2][k]) + we * fabs(y);
+        if (d == 1) return fabs(vp * g->sn[2][k]) + we * fabs(x);
+        return we + wp;
+    }
+    case ORC_DUBINS4D: {
+        long k = axis_index(g, node, 2);
+        double v = g->x[3][axis_index(g, node, 3)];
+        if (d == 0) return fabs(v * g->cs[2][k]);
+        if (d == 1) return fabs(v * g->sn[2][k]);
+        if (d == 2) return dy->prm[0];
+        return dy->prm[1];
+    }
+    }
+    return 0.0;
+}
+
+/* Sec. 4: global Lax-Friedrichs dissipation coefficients. */
+static void compute_alpha(const ogrid *g, const odyn *dy, double *alpha)
+{
+    for (int d = 0; d < g->nd; ++d) {
+        double m = 0.0;
+        for (long node = 0; node < g->total; ++node) {
+            double b = speed_bound(g, dy, node, d);
+            if (b > m) m = b;
+        }
+        alpha[d] = m;
+    }
+}
+
+/* Sec. 4 CFL condition, reading R5: the step that makes
+ * dt * sum_d alpha_d/dx_d equal to cfl. */
+static double cfl_dt(const ogrid *g, const double *alpha, double cfl)
+{
+    double rate = 0.0;
+    for (int d = 0; d < g->nd; ++d) rate += alpha[d] / g->dx[d];
+    if (rate <= 0.0) return INFINITY;
+    return cfl / rate;
+}
+
+/* Sec. 4, Lax-Friedrichs:
+ *   Hhat = H(x, (p+ + p-)/2) - sum_d alpha_d (p+_d - p-_d)/2,
+ * and the semi-discrete right-hand side L(V) = -Hhat (from V_t + H = 0). */
+static double rhs_at(const ogrid *g, const odyn *dy, int scheme,
+                     const double *alpha, const double *v, long node)
+{
+    double pm[ORC_MAXD], pp[ORC_MAXD], pbar[ORC_MAXD];
+    for (int d = 0; d < g->nd; ++d) {
+        derivs_at(g, v, node, d, scheme, &pm[d], &pp[d]);
+        pbar[d] = (pp[d] + pm[d]) / 2.0;
+    }
+    double hhat = hamiltonian(g, dy, node, pbar);
+    for (int d = 0; d < g->nd; ++d) hhat -= alpha[d] * ((pp[d] - pm[d]) / 2.0);
+    return -hhat;
+}
+
+static void rhs_all(const ogrid *g, const odyn *dy, int scheme,
+                    const double *alpha, const double *v, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long node = 0; node < g->total; ++node)
+        out[node] = rhs_at(g, dy, scheme, alpha, v, node);
+}
+
+/* Sec. 5 (odeCFL listing) and readings R7, R8, R11: one TVD-RK step of size h
+ * applied in place to v.  w1, w2, l are scratch arrays of the grid size. */
+static void rk_step(const ogrid *g, const odyn *dy, int scheme, int order,
+                    const double *alpha, double h, double *v, const double *v0,
+                    int mode, double *w1, double *w2, double *l)
+{
+    long n = g->total;
+    if (order == 1) {
+        rhs_all(g, dy, scheme, alpha, v, l);
+        for (long k = 0; k < n; ++k) v[k] = v[k] + h * l[k];
+    } else if (order == 2) {
+        rhs_all(g, dy, scheme, alpha, v, l);
+        for (long k = 0; k < n; ++k) w1[k] = v[k] + h * l[k];
+        rhs_all(g, dy, scheme, alpha, w1, l);
+        for (long k = 0; k < n; ++k) {
+            double v2 = w1[k] + h * l[k];
+            v[k] = (v[k] + v2) / 2.0;
+        }
+    } else {
+        rhs_all(g, dy, scheme, alpha, v, l);
+        for (long k = 0; k < n; ++k) w1[k] = v[k] + h * l[k];
+        rhs_all(g, dy, scheme, alpha, w1, l);
+        for (long k = 0; k < n; ++k) {
+            double v2 = w1[k] + h * l[k];
+            w2[k] = (3.0 * v[k] + v2) / 4.0;
+        }
+        rhs_all(g, dy, scheme, alpha, w2, l);
+        for (long k = 0; k < n; ++k) {
+            double v3 = w2[k] + h * l[k];
+            v[k] = (v[k] + 2.0 * v3) / 3.0;
+        }
+    }
+    if (mode == ORC_TUBE)
+        for (long k = 0; k < n; ++k)
+            if (v0[k] < v[k]) v[k] = v0[k];
+}
+
+static int setup(ogrid *g, odyn *dy, int nd, const long *n, const double *lo,
+                 const double *hi, unsigned pmask, int dyn, const double *prm,
+                 int nprm)
+{
+    if (grid_init(g, nd, n, lo, hi, pmask) != 0) return -1;
+    dy->kind = dyn;
+    memset(dy->prm, 0, sizeof(dy->prm));
+    for (int k = 0; k < nprm && k < 8; ++k) dy->prm[k] = prm[k];
+    return 0;
+}
+
+/* --------------------------------------------------------- exported API */
+
+/* alpha per axis, the CFL step and the step count of a solve over [t0, tf]
+ * (readings R4-R6). */
+int orc_schedule(int nd, const long *n, const double *lo, const double *hi,
+                 unsigned pmask, int dyn, const double *prm, int nprm,
+                 double cfl, double t0, double tf, double *alpha_out,
+                 double *dt_out, long *nsteps_out, double *tend_out)
+{
+    ogrid g;
+    odyn dy;
+    memset(&g, 0, sizeof(g));
+    if (setup(&g, &dy, nd, n, lo, hi, pmask, dyn, prm, nprm) != 0) {
+        grid_free(&g);
+        return -1;
+    }
+    compute_alpha(&g, &dy, alpha_out);
+    double dt = cfl_dt(&g, alpha_out, cfl);
+    *dt_out = dt;
+    long steps = 0;
+    double t = t0;
+    const double eps = 100.0 * 2.220446049250313e-16;
+    if (tf > t0) {
+        while (tf - t >= eps * (tf - t0)) {
+            double h = dt < tf - t ? dt : tf - t;
+            t = t + h;
+            ++steps;
+        }
+    }
+    *nsteps_out = steps;
+    *tend_out = t;
+    grid_free(&g);
+    return 0;
+}
+
+/* p- and p+ along axis `axis` at every node of v (Sec. 3). */
+int orc_derivs(int nd, const long *n, const double *lo, const double *hi,
+               unsigned pmask, int scheme, int axis, const double *v,
+               double *pm, double *pp)
+{
+    ogrid g;
+    memset(&g, 0, sizeof(g));
+    if (grid_init(&g, nd, n, lo, hi, pmask) != 0) {
+        grid_free(&g);
+        return -1;
+    }
+    for (long node = 0; node < g.total; ++node)
+        derivs_at(&g, v, node, axis, scheme, &pm[node], &pp[node]);
+    grid_free(&g);
+    return 0;
+}
+
+/* L(V) = -Hhat at the listed nodes (Sec. 4), for a given alpha. */
+int orc_rhs_at(int nd, const long *n, const double *lo, const double *hi,
+               unsigned pmask, int dyn, const double *prm, int nprm,
+               int scheme, const double *alpha, const double *v, long count,
+               const long *nodes, double *out)
+{
+    ogrid g;
+    odyn dy;
+    memset(&g, 0, sizeof(g));
+    if (setup(&g, &dy, nd, n, lo, hi, pmask, dyn, prm, nprm) != 0) {
+        grid_free(&g);
+        return -1;
+    }
+    for (long k = 0; k < count; ++k)
+        out[k] = rhs_at(&g, &dy, scheme, alpha, v, nodes[k]);
+    grid_free(&g);
+    return 0;
+}
+
+/* Advance v in place by `nsteps` TVD-RK steps of size h each (h is used as
+ * given), with the tube update when mode is ORC_TUBE. alpha is supplied. */
+int orc_steps(int nd, const long *n, const double *lo, const double *hi,
+              unsigned pmask, int dyn, const double *prm, int nprm,
+              int scheme, int order, const double *alpha, double h, long nsteps,
+              double *v, const double *v0, int mode)
+{
+    ogrid g;
+    odyn dy;
+    memset(&g, 0, sizeof(g));
+    if (setup(&g, &dy, nd, n, lo, hi, pmask, dyn, prm, nprm) != 0) {
+        grid_free(&g);
+        return -1;
+    }
+    size_t bytes = sizeof(double) * (size_t)g.total;
+    double *w1 = (double *)malloc(bytes), *w2 = (double *)malloc(bytes),
+           *l = (double *)malloc(bytes);
+    int rc = 0;
+    if (!w1 || !w2 || !l) {
+        rc = -2;
+    } else {
+        for (long s = 0; s < nsteps; ++s)
+            rk_step(&g, &dy, scheme, order, alpha, h, v, v0, mode, w1, w2, l);
+    }
+    free(w1);
+    free(w2);
+    free(l);
+    grid_free(&g);
+    return rc;
+}
+
+/* Full solve over [t0, tf] from V0 (Sec. 5 time loop with readings R4-R6,
+ * R11).  v_out receives V(tf).  Returns the step count or a negative code. */
+long orc_solve(int nd, const long *n, const double *lo, const double *hi,
+               unsigned pmask, int dyn, const double *prm, int nprm,
+               int scheme, int order, double cfl, const double *v0,
+               double *v_out, double t0, double tf, int mode,
+               double *alpha_out, double *dt_out)
+{
+    ogrid g;
+    odyn dy;
+    memset(&g, 0, sizeof(g));
+    if (setup(&g, &dy, nd, n, lo, hi, pmask, dyn, prm, nprm) != 0) {
+        grid_free(&g);
+        return -1;
+    }
+    double alpha[ORC_MAXD] = {0, 0, 0, 0};
+    compute_alpha(&g, &dy, alpha);
+    double dt = cfl_dt(&g, alpha, cfl);
+    for (int d = 0; d < nd; ++d) alpha_out[d] = alpha[d];
+    *dt_out = dt;
+
+    size_t bytes = sizeof(double) * (size_t)g.total;
+    memcpy(v_out, v0, bytes);
+    double *w1 = (double *)malloc(bytes), *w2 = (double *)malloc(bytes),
+           *l = (double *)malloc(bytes);
+    if (!w1 || !w2 || !l) {
+        free(w1);
+        free(w2);
+        free(l);
+        grid_free(&g);
+        return -2;
+    }
+    long steps = 0;
+    double t = t0;
+    const double eps = 100.0 * 2.220446049250313e-16;
+    if (tf > t0) {
+        while (tf - t >= eps * (tf - t0)) {
+            double h = dt < tf - t ? dt : tf - t;
+            rk_step(&g, &dy, scheme, order, alpha, h, v_out, v0, mode, w1, w2, l);
+            t = t + h;
+            ++steps;
+        }
+    }
+    free(w1);
+    free(w2);
+    free(l);
+    grid_free(&g);
+    return steps;
+}
+
+/* number of host threads used by the node loops (0 or less: all cores) */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

@@ -1,0 +1,350 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test names what a plausible mistake in the oracle would break:
+direction of the one-sided differences, ENO/WENO tables and weights, the
+Lax-Friedrichs sign, alpha and the CFL step, the RK combinations, the tube
+update and the signs of the game Hamiltonians.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2507_11542_amd import inputs, metrics
+
+PI = math.pi
+
+
+# ---------------------------------------------------------------- T1 exact shift
+@pytest.mark.parametrize("ndim,axis,b", [(1, 0, 2.0), (1, 0, -2.0), (2, 1, 1.5),
+                                         (3, 0, -1.0), (3, 2, 3.0), (4, 3, 1.0)])
+def test_exact_shift_upwind1_euler(orc, ndim, axis, b):
+    """x' = b e_axis, first-order upwind, forward Euler, CFL 1 on a periodic
+    grid moves V by exactly one cell (Sec. 3.1 upwind rule with the LF
+    dissipation alpha = |b|): V^1 = roll(V^0, -sign(b)) along the axis."""
+    n = tuple([8, 6, 5, 7][:ndim])
+    n = tuple(32 if d == axis else n[d] for d in range(ndim))
+    lo = tuple(0.0 for _ in n)
+    hi = tuple(1.0 for _ in n)
+    per = tuple(True for _ in n)
+    bvec = tuple(b if d == axis else 0.0 for d in range(ndim))
+    v0 = inputs.random_field(n, seed=ndim + axis)
+    dx = 1.0 / 32
+    out, alpha, dt, k = orc.solve(v0, n, lo, hi, per, "translation", bvec, "upwind1", 1,
+                                  1.0, 0.0, dx / abs(b), "set")
+    assert k == 1
+    assert alpha[axis] == abs(b)
+    assert dt == pytest.approx(dx / abs(b), rel=1e-15)
+    expect = np.roll(v0, -1 if b > 0 else 1, axis=axis)
+    assert np.abs(out - expect).max() <= 1e-14 * np.abs(v0).max()
+
+
+# ------------------------------------------------------- T2 polynomial reproduction
+def _poly_line(n, lo, hi, coeffs):
+    x = inputs.node_coords((n,), (lo,), (hi,), (False,))[0]
+    v = np.polyval(coeffs, x)
+    dv = np.polyval(np.polyder(coeffs), x)
+    return x, v, dv
+
+
+@pytest.mark.parametrize("scheme,deg,w", [("upwind1", 1, 0), ("eno2", 2, 2), ("weno5", 3, 3)])
+def test_polynomial_reproduction(orc, scheme, deg, w):
+    """UPWIND1 is exact on linear, ENO2 on quadratic, WENO5 on cubic data (for
+    any weights: every WENO candidate is exact there) at nodes whose stencil
+    needs no ghost (Sec. 3.1-3.3)."""
+    rng = np.random.default_rng(deg)
+    coeffs = rng.uniform(-2, 2, deg + 1)
+    n = 23
+    x, v, dv = _poly_line(n, -1.3, 0.9, coeffs)
+    pm, pp = orc.derivs(v, (n,), (-1.3,), (0.9,), (False,), scheme, 0)
+    inner = slice(w, n - w) if w else slice(None)
+    scale = np.abs(dv).max() + 1.0
+    assert np.abs(pm[inner] - dv[inner]).max() <= 1e-12 * scale
+    assert np.abs(pp[inner] - dv[inner]).max() <= 1e-12 * scale
+
+
+def test_eno2_not_exact_on_cubic(orc):
+    """The ENO2 correction is second order: a cubic is not reproduced."""
+    x, v, dv = _poly_line(23, -1.0, 1.0, [1.0, 0.0, 0.0, 0.0])
+    pm, pp = orc.derivs(v, (23,), (-1.0,), (1.0,), (False,), "eno2", 0)
+    assert np.abs(pm[2:-2] - dv[2:-2]).max() > 1e-4
+
+
+def test_linear_extrapolation_ghosts(orc):
+    """Linear data stays linear through the ghost rule v_{-k} = v_0 + k(v_0 - v_1):
+    every scheme is exact on a line at every node, boundaries included."""
+    x, v, dv = _poly_line(17, 0.0, 2.0, [0.7, -0.2])
+    for scheme in ("upwind1", "eno2", "weno5"):
+        pm, pp = orc.derivs(v, (17,), (0.0,), (2.0,), (False,), scheme, 0)
+        assert np.abs(pm - 0.7).max() < 1e-13
+        assert np.abs(pp - 0.7).max() < 1e-13
+
+
+@pytest.mark.parametrize("scheme,order", [("eno2", 1.95), ("weno5", 4.8)])
+def test_derivative_order_on_smooth_data(orc, scheme, order):
+    """On smooth periodic data ENO2 is second and WENO5 fifth order accurate.
+    Fifth order needs the ideal linear weights (0.1, 0.6, 0.3) in the right
+    places: any other weights fall back to third order."""
+    errs = []
+    for n in (40, 80, 160):
+        x = inputs.node_coords((n,), (0.0,), (1.0,), (True,))[0]
+        v = np.sin(2 * PI * x)
+        pm, pp = orc.derivs(v, (n,), (0.0,), (1.0,), (True,), scheme, 0)
+        ex = 2 * PI * np.cos(2 * PI * x)
+        errs.append(max(np.abs(pm - ex).max(), np.abs(pp - ex).max()))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) >= order, (errs, rates)
+
+
+@pytest.mark.parametrize("scheme", ["eno2", "weno5"])
+def test_non_oscillatory_at_kink(orc, scheme):
+    """|x - xc| with the kink between two nodes: the left derivative at the node
+    left of the kink only uses the smooth side, so it is -1 (ENO exactly,
+    WENO up to the epsilon-sized weight of the crossing stencils)."""
+    n = 40
+    x = inputs.node_coords((n,), (-1.0,), (1.0,), (False,))[0]
+    dx = x[1] - x[0]
+    v = np.abs(x - (x[20] + 0.5 * dx))
+    pm, pp = orc.derivs(v, (n,), (-1.0,), (1.0,), (False,), scheme, 0)
+    tol = 1e-14 if scheme == "eno2" else 1e-6
+    assert abs(pm[20] + 1.0) < tol
+    assert abs(pp[21] - 1.0) < tol
+    assert np.abs(pm[:18] + 1.0).max() < tol
+    assert np.abs(pp[23:] - 1.0).max() < tol
+
+
+# ------------------------------------------------------------ T3 ball growth
+def test_ball_grows_at_unit_speed(orc):
+    """x' = u, |u|_2 <= 1 (H = |p|): the disk of radius r grows to r + t and
+    V = |x| - r - t near the front (sign convention of V_t + H = 0)."""
+    p = inputs.Problem("ball", (161, 161), (-2.0, -2.0), (2.0, 2.0), (False, False),
+                       "ball", (1.0,), "weno5", 3, 0.8, 0.0, 0.5, "set", radius=0.5)
+    out, alpha, dt, k = orc.solve(p.v0(), *p.grid_args(), p.dynamics, p.params,
+                                  p.scheme, p.order, p.cfl, p.t0, p.tf, p.mode)
+    assert list(alpha) == [1.0, 1.0]
+    X, Y = np.meshgrid(*p.coords(), indexing="ij")
+    R = np.sqrt(X ** 2 + Y ** 2)
+    ann = np.abs(R - 1.0) < 0.3
+    assert np.abs(out - (R - 1.0))[ann].max() < 2e-5
+    ex = R - 1.0
+    assert metrics.hausdorff_cells(out, ex, p.periodic) < 0.05
+
+
+# ----------------------------------------------------- T4 convergence order
+@pytest.mark.parametrize("scheme,order,sizes,rate", [
+    ("upwind1", 1, (40, 80, 160), 0.9),
+    ("eno2", 2, (80, 160, 320), 1.7),
+    ("weno5", 3, (40, 80, 160), 2.7),
+])
+def test_translation_convergence_order(orc, scheme, order, sizes, rate):
+    """Smooth periodic translation V0 = sin(2 pi x): the observed order of the
+    whole scheme (space and TVD-RK time stepping) reaches its design order."""
+    errs = []
+    for n in sizes:
+        x = inputs.node_coords((n,), (0.0,), (1.0,), (True,))[0]
+        v0 = np.sin(2 * PI * x)
+        out, _, _, _ = orc.solve(v0, (n,), (0.0,), (1.0,), (True,), "translation", (1.0,),
+                                 scheme, order, 0.8, 0.0, 0.3, "set")
+        errs.append(np.abs(out - np.sin(2 * PI * (x + 0.3))).mean())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert rates[-1] >= rate, (errs, rates)
+
+
+def test_rk3_is_third_order_in_time(orc):
+    """Fixed fine space, dt halved: RK3 error falls by ~8, RK2 by ~4, RK1 by ~2
+    (pins the TVD-RK stage combinations of Sec. 5).  Uses H = -b.p with
+    WENO5 on a fine periodic grid so the spatial error is negligible."""
+    n = 400
+    x = inputs.node_coords((n,), (0.0,), (1.0,), (True,))[0]
+    v0 = np.sin(2 * PI * x)
+    ref = orc.steps(v0, None, (n,), (0.0,), (1.0,), (True,), "translation", (1.0,),
+                    "weno5", 3, [1.0], 0.0025 / 16, 16 * 40)
+    for order, want in ((1, 1.8), (2, 3.6), (3, 6.5)):
+        e = []
+        for k in (1, 2):
+            h = 0.0025 / k
+            out = orc.steps(v0, None, (n,), (0.0,), (1.0,), (True,), "translation", (1.0,),
+                            "weno5", order, [1.0], h, 40 * k)
+            e.append(np.abs(out - ref).max())
+        assert e[0] / e[1] > want, (order, e)
+
+
+# -------------------------------------------------------- T5/T6 tube logic
+def test_tube_invariant_every_step(orc):
+    """Tube mode keeps V(t) <= V0 at every node after every step (bitwise)."""
+    p = inputs.rel_dubins_3d(n=(21, 19, 16), tf=0.3)
+    v0 = p.v0()
+    alpha, dt, k, _ = orc.schedule(*p.grid_args(), p.dynamics, p.params, p.cfl, 0.0, 0.3)
+    v = v0.copy()
+    for _ in range(k):
+        v = orc.steps(v, v0, *p.grid_args(), p.dynamics, p.params, "weno5", 3, alpha, dt, 1,
+                      mode="tube")
+        assert np.all(v <= v0)
+    vs = orc.steps(v0, v0, *p.grid_args(), p.dynamics, p.params, "weno5", 3, alpha, dt, k,
+                   mode="set")
+    assert np.any(vs > v0)  # the set evolution alone would leave the tube
+
+
+@pytest.mark.parametrize("speed", [0.7, -0.7])
+def test_tube_on_plane_growth_and_shrink(orc, speed):
+    """V0 = plane n.x - c (|n| = 1) under H = s|p|: every scheme is exact on
+    linear data, ghosts included, so the set evolves to V0 - s t.  Growing
+    (s > 0) the value only falls and the tube equals the set; shrinking
+    (s < 0) the value only rises and the tube stays at V0 bitwise."""
+    n, lo, hi, per = (23, 19), (-1.0, -2.0), (1.5, 1.0), (False, False)
+    X, Y = np.meshgrid(*inputs.node_coords(n, lo, hi, per), indexing="ij")
+    v0 = np.ascontiguousarray(0.6 * X - 0.8 * Y - 0.1)
+    tf = 0.37
+    a, *_ = orc.solve(v0, n, lo, hi, per, "ball", (speed,), "weno5", 3, 0.8, 0, tf, "set")
+    b, *_ = orc.solve(v0, n, lo, hi, per, "ball", (speed,), "weno5", 3, 0.8, 0, tf, "tube")
+    assert np.abs(a - (v0 - speed * tf)).max() <= 1e-13
+    if speed > 0:
+        assert np.abs(a - b).max() <= 1e-13
+    else:
+        assert np.array_equal(b, v0)
+
+
+# ---------------------------------------------------- T7 alpha / dt / steps
+def test_schedule_values(orc):
+    """alpha = max over nodes of the control-set bound on |f_i|; dt from CFL 0.8;
+    step counts of the three single-solve workloads.  Hand values:
+    double integrator alpha = (max|x2|, umax) = (1, 1), dt = 0.8/(1/0.02+1/0.02);
+    relative Dubins alpha = (|-5-5| + 1*10, 5 cos(pi/202) + 1*20, 1+1);
+    4-D Dubins alpha = (4*1, 4 cos(pi/122), 1, 1)."""
+    a, dt, k, t = orc.schedule((101, 101), (-1, -1), (1, 1), (0, 0), "double_integrator",
+                               (1.0,), 0.8, 0.0, 1.0)
+    assert list(a) == [1.0, 1.0] and dt == 0.008 and k == 125 and t == 1.0
+    a, dt, k, t = orc.schedule((101,) * 3, (-6, -10, -PI), (20, 10, PI), (0, 0, 1),
+                               "rel_dubins", (5, 5, 1, 1), 0.8, 0.0, 2.8)
+    assert a[0] == 20.0 and a[2] == 2.0
+    assert a[1] == pytest.approx(5 * math.cos(PI / 202) + 20.0, rel=1e-15)
+    rate = 20 / 0.26 + a[1] / 0.2 + 2 / (2 * PI / 101)
+    assert dt == pytest.approx(0.8 / rate, rel=1e-14)
+    assert dt == pytest.approx(3.41779046737e-3, rel=1e-10)
+    assert k == 820 == math.ceil(2.8 / dt)
+    a, dt, k, t = orc.schedule((61,) * 4, (-5, -5, -PI, 0), (5, 5, PI, 4), (0, 0, 1, 0),
+                               "dubins4d", (1, 1), 0.8, 0.0, 2.0)
+    assert a[0] == 4.0 and a[2] == 1.0 and a[3] == 1.0
+    assert a[1] == pytest.approx(4 * math.cos(PI / 122), rel=1e-14)
+    assert dt == pytest.approx(1.1004051661e-2, rel=1e-9)
+    assert k == 182
+    # the listing's CFL factor 0.32 gives 2049 relative-Dubins steps
+    a, dt, k, t = orc.schedule((101,) * 3, (-6, -10, -PI), (20, 10, PI), (0, 0, 1),
+                               "rel_dubins", (5, 5, 1, 1), 0.32, 0.0, 2.8)
+    assert k == 2049
+
+
+def test_schedule_last_step_truncated(orc):
+    """The last step is cut to land on tf; a horizon ending at 0 with t0 < 0
+    terminates (Sec. 5 loop with the relative epsilon)."""
+    a, dt, k, t = orc.schedule((10,), (0.0,), (1.0,), (True,), "translation", (1.0,),
+                               0.8, -0.25, 0.0)
+    assert dt == pytest.approx(0.08)
+    assert k == 4 and abs(t) < 1e-15
+
+
+# ------------------------------------------------------------ T8 symmetry
+def test_symmetry_double_integrator(orc):
+    """The double integrator and the disk are invariant under x -> -x."""
+    p = inputs.double_integrator_2d()
+    out, *_ = orc.solve(p.v0(), *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
+                        p.cfl, p.t0, p.tf, p.mode)
+    assert np.abs(out - out[::-1, ::-1]).max() <= 1e-12
+
+
+def _mirror_psi(v):
+    # psi_k -> -psi_k maps node k to (N - k) mod N on the periodic axis
+    idx = (-np.arange(v.shape[2])) % v.shape[2]
+    return v[:, ::-1, :][:, :, idx]
+
+
+def test_symmetry_rel_dubins(orc):
+    """(x, y, psi) -> (x, -y, -psi) maps the relative-Dubins game to itself."""
+    p = inputs.rel_dubins_3d(n=(27, 21, 24), tf=0.5)
+    out, *_ = orc.solve(p.v0(), *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
+                        p.cfl, p.t0, p.tf, p.mode)
+    assert np.abs(out - _mirror_psi(out)).max() <= 1e-12
+
+
+def test_symmetry_dubins4d(orc):
+    """(x, y, th, v) -> (x, -y, -th, v) maps the 4-D Dubins car to itself."""
+    p = inputs.dubins4d(n=(15, 15, 12, 9), tf=0.3)
+    out, *_ = orc.solve(p.v0(), *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
+                        p.cfl, p.t0, p.tf, p.mode)
+    idx = (-np.arange(12)) % 12
+    mir = out[:, ::-1, :, :][:, :, idx, :]
+    assert np.abs(out - mir).max() <= 1e-12
+
+
+# --------------------------------------------------- T9 brute-force tube
+def _double_integrator_brute(x1, x2, umax, tf, r, m=121):
+    """min over bang-bang controls with at most one switch and stop times
+    s <= tf of |x(s)| - r.  The costate p2 is affine in time, so the optimal
+    control of this Mayer problem switches at most once (Pontryagin)."""
+    ts = np.linspace(0.0, tf, m)
+    best = np.full(x1.shape, np.inf)
+    for u0 in (-umax, umax):
+        for i, tau in enumerate(ts):
+            a1 = x1 + x2 * tau + u0 * tau ** 2 / 2
+            a2 = x2 + u0 * tau
+            rr = ts[i:] - tau
+            b1 = a1[:, None] + a2[:, None] * rr[None, :] - u0 * rr[None, :] ** 2 / 2
+            b2 = a2[:, None] - u0 * rr[None, :]
+            best = np.minimum(best, np.sqrt(b1 ** 2 + b2 ** 2).min(axis=1))
+    return best - r
+
+
+def test_double_integrator_tube_brute_force(orc):
+    """The ENO2/RK2 tube of the double integrator matches the exact reach tube
+    from trajectory enumeration: zero sets within half a cell, values within
+    0.01 near the front."""
+    p = inputs.double_integrator_2d()
+    out, *_ = orc.solve(p.v0(), *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
+                        p.cfl, p.t0, p.tf, p.mode)
+    X1, X2 = np.meshgrid(*p.coords(), indexing="ij")
+    vb = _double_integrator_brute(X1.ravel(), X2.ravel(), 1.0, 1.0, 0.5).reshape(X1.shape)
+    assert metrics.hausdorff_cells(out, vb, p.periodic) < 0.5
+    band = np.abs(vb) < 0.1
+    assert np.abs(out - vb)[band].max() < 0.01
+
+
+# ------------------------------------ T10 zero turn rates: closed-form sets
+def test_rel_dubins_zero_turn_is_capsule(orc):
+    """With we = wp = 0 every psi slice translates at w = (-ve + vp cos psi,
+    vp sin psi); the tube of the disk is the capsule swept over [0, T]."""
+    ve = vp = 1.0
+    T, r = 2.0, 2.0
+    p = inputs.Problem("capsule", (97, 97, 16), (-12.0, -12.0, -PI), (12.0, 12.0, PI),
+                       (False, False, True), "rel_dubins", (ve, vp, 0.0, 0.0), "weno5", 3,
+                       0.8, 0.0, T, "tube", radius=r)
+    out, alpha, dt, k = orc.solve(p.v0(), *p.grid_args(), p.dynamics, p.params, p.scheme,
+                                  p.order, p.cfl, p.t0, p.tf, p.mode)
+    X, Y, PS = np.meshgrid(*p.coords(), indexing="ij")
+    wx, wy = -ve + vp * np.cos(PS), vp * np.sin(PS)
+    ww = wx ** 2 + wy ** 2
+    s = np.where(ww > 0, np.clip(-(X * wx + Y * wy) / np.where(ww > 0, ww, 1.0), 0, T), 0.0)
+    exact = np.sqrt((X + wx * s) ** 2 + (Y + wy * s) ** 2) - r
+    assert metrics.hausdorff_cells(out, exact, p.periodic) < 1.0
+
+
+def test_dubins4d_zero_controls_is_shifted_disk(orc):
+    """With w = a = 0 the 4-D car translates at (v cos th, v sin th): the
+    reachable set at t is the disk shifted by -t (v cos th, v sin th)."""
+    p = inputs.dubins4d(n=(41, 41, 8, 5), w_max=0.0, a_max=0.0, tf=1.0)
+    p = p.with_(lo=(-8.0, -8.0, -PI, 0.0), hi=(8.0, 8.0, PI, 2.0))
+    out, *_ = orc.solve(p.v0(), *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
+                        p.cfl, p.t0, p.tf, p.mode)
+    X, Y, TH, V = np.meshgrid(*p.coords(), indexing="ij")
+    exact = np.sqrt((X + V * np.cos(TH)) ** 2 + (Y + V * np.sin(TH)) ** 2) - 1.0
+    assert metrics.hausdorff_cells(out, exact, p.periodic) < 1.0
+
+
+def test_rhs_at_matches_steps(orc):
+    """Pointwise L(V) from rhs_at reproduces one forward-Euler step."""
+    p = inputs.rel_dubins_3d(n=(13, 11, 10), tf=0.1)
+    v0 = p.v0()
+    alpha, dt, k, _ = orc.schedule(*p.grid_args(), p.dynamics, p.params, 0.8, 0.0, 0.1)
+    v1 = orc.steps(v0, v0, *p.grid_args(), p.dynamics, p.params, "weno5", 1, alpha, dt, 1)
+    nodes = inputs.sample_nodes(p.n, 50, seed=3)
+    l = orc.rhs_at(v0, *p.grid_args(), p.dynamics, p.params, "weno5", alpha, nodes)
+    assert np.abs(v0.ravel()[nodes] + dt * l - v1.ravel()[nodes]).max() == 0.0
