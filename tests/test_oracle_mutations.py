@@ -1,0 +1,63 @@
+"""The oracle pins catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle source (on the CPU),
+builds it, points the oracle shim at the mutated build and runs the pin suite:
+the suite must fail.  A mutation that survives means the pins do not
+constrain that part of the oracle.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hj_oracle.c")
+
+MUTATIONS = {
+    "upwind_directions_swapped": ("*pm = (vc - vm) / dx;\n        *pp = (vp - vc) / dx;",
+                                  "*pm = (vp - vc) / dx;\n        *pp = (vc - vm) / dx;"),
+    "eno2_right_correction_sign": ("*pp = d1[2] - dx * eno_pick", "*pp = d1[2] + dx * eno_pick"),
+    "eno2_picks_larger": ("return fabs(a) <= fabs(b) ? a : b;", "return fabs(a) <= fabs(b) ? b : a;"),
+    "eno2_second_difference_scale": ("(d1[k + 1] - d1[k]) / (2.0 * dx)", "(d1[k + 1] - d1[k]) / dx"),
+    "weno_linear_weights_swapped": ("double a1 = 0.1 /", "double a1 = 0.3 /"),
+    "weno_candidate_coefficient": ("11.0 * v3 / 6.0", "10.0 * v3 / 6.0"),
+    "weno_smoothness_term": ("0.25 * (v2 - v4) * (v2 - v4)", "0.25 * (v2 + v4) * (v2 - v4)"),
+    "weno_right_stencil_order": ("weno5(d1[5], d1[4], d1[3], d1[2], d1[1])",
+                                 "weno5(d1[1], d1[2], d1[3], d1[4], d1[5])"),
+    "lf_dissipation_sign": ("hhat -= alpha[d] *", "hhat += alpha[d] *"),
+    "rhs_sign": ("    return -hhat;\n}", "    return hhat;\n}"),
+    "rk2_combination": ("v[k] = (v[k] + v2) / 2.0;", "v[k] = v2;"),
+    "rk3_middle_stage": ("w2[k] = (3.0 * v[k] + v2) / 4.0;", "w2[k] = (v[k] + v2) / 2.0;"),
+    "rk3_last_stage": ("v[k] = (v[k] + 2.0 * v3) / 3.0;", "v[k] = (2.0 * v[k] + v3) / 3.0;"),
+    "tube_uses_max": ("if (v0[k] < v[k]) v[k] = v0[k];", "if (v0[k] > v[k]) v[k] = v0[k];"),
+    "ghost_extrapolation_sign": ("return v0 + (double)(-j) * (v0 - v1);",
+                                 "return v0 - (double)(-j) * (v0 - v1);"),
+    "periodic_wrap_offset": ("long jj = ((j % n) + n) % n;", "long jj = ((j % n) + n + 1) % n;"),
+    "rel_dubins_rotation_sign": ("fabs(p[0] * y - p[1] * x - p[2])", "fabs(p[0] * y + p[1] * x - p[2])"),
+    "rel_dubins_pursuer_sign": ("+ wp * fabs(p[2]);", "- wp * fabs(p[2]);"),
+    "rel_dubins_drift_sign": ("-p[0] * (-ve + vp * c)", "-p[0] * (ve + vp * c)"),
+    "dubins4d_turn_sign": ("+ wm * fabs(p[2])", "- wm * fabs(p[2])"),
+    "double_integrator_drift_sign": ("return -p[0] * x2 +", "return p[0] * x2 +"),
+    "alpha_double_integrator": ("if (d == 0) return fabs(g->x[1][axis_index(g, node, 1)]);",
+                                "if (d == 0) return dy->prm[0];"),
+    "cfl_rate": ("rate += alpha[d] / g->dx[d];", "rate += alpha[d] * g->dx[d];"),
+    "periodic_cell_size": ("(hi[d] - lo[d]) / (double)n[d]", "(hi[d] - lo[d]) / (double)(n[d] - 1)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor not found: " + name
+    mut = tmp_path / "hj_oracle_mut.c"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "libhj_oracle_mut.so"
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    "-std=c99", "-o", str(lib), str(mut), "-lm"], check=True)
+    env = dict(os.environ, HJ_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "mutation %s survived the pins:\n%s" % (name, r.stdout[-2000:])

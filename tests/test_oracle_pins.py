@@ -214,6 +214,10 @@ def test_schedule_values(orc):
     a, dt, k, t = orc.schedule((101, 101), (-1, -1), (1, 1), (0, 0), "double_integrator",
                                (1.0,), 0.8, 0.0, 1.0)
     assert list(a) == [1.0, 1.0] and dt == 0.008 and k == 125 and t == 1.0
+    a, dt, k, t = orc.schedule((41, 21), (-1, -3), (1, 2), (0, 0), "double_integrator",
+                               (0.5,), 0.8, 0.0, 1.0)
+    assert list(a) == [3.0, 0.5]
+    assert dt == pytest.approx(0.8 / (3.0 / 0.05 + 0.5 / 0.25), rel=1e-15)
     a, dt, k, t = orc.schedule((101,) * 3, (-6, -10, -PI), (20, 10, PI), (0, 0, 1),
                                "rel_dubins", (5, 5, 1, 1), 0.8, 0.0, 2.8)
     assert a[0] == 20.0 and a[2] == 2.0
@@ -348,3 +352,52 @@ def test_rhs_at_matches_steps(orc):
     nodes = inputs.sample_nodes(p.n, 50, seed=3)
     l = orc.rhs_at(v0, *p.grid_args(), p.dynamics, p.params, "weno5", alpha, nodes)
     assert np.abs(v0.ravel()[nodes] + dt * l - v1.ravel()[nodes]).max() == 0.0
+
+
+# ------------------- T10b the turn-rate and acceleration terms of the games
+def test_rel_dubins_evader_rotation(orc):
+    """ve = vp = wp = 0: the evader only rotates (x, y) at |we| <= w and
+    maximises, so V(x, T) = max over |th| <= w T of V0(R_th x) for a V0 that
+    does not depend on psi (the disk of radius 1.5 centred at (3, 0))."""
+    w, T = 1.0, 0.25
+    n, lo, hi, per = (81, 81, 8), (-6.0, -6.0, -PI), (6.0, 6.0, PI), (False, False, True)
+    X, Y, _ = np.meshgrid(*inputs.node_coords(n, lo, hi, per), indexing="ij")
+    v0 = np.ascontiguousarray(np.sqrt((X - 3) ** 2 + Y ** 2) - 1.5)
+    out, *_ = orc.solve(v0, n, lo, hi, per, "rel_dubins", (0.0, 0.0, w, 0.0), "weno5", 3,
+                        0.8, 0.0, T, "set")
+    best = np.full(X.shape, -np.inf)
+    for th in np.linspace(-w * T, w * T, 1001):
+        c, s = math.cos(th), math.sin(th)
+        best = np.maximum(best, np.sqrt((c * X - s * Y - 3) ** 2 + (s * X + c * Y) ** 2) - 1.5)
+    assert metrics.hausdorff_cells(out, best, per) < 0.6
+    assert np.abs(out - best)[np.abs(best) < 0.3].max() < 0.06
+
+
+def test_rel_dubins_pursuer_heading(orc):
+    """ve = vp = we = 0: the pursuer turns psi at |wp| <= w and minimises, so a
+    V0 = |psi| - 0.5 set grows in psi at rate w: V = max(|psi| - w T, 0) - 0.5."""
+    n, lo, hi, per = (9, 9, 121), (-1.0, -1.0, -PI), (1.0, 1.0, PI), (False, False, True)
+    _, _, PS = np.meshgrid(*inputs.node_coords(n, lo, hi, per), indexing="ij")
+    v0 = np.ascontiguousarray(np.abs(PS) - 0.5)
+    T = 0.6
+    out, *_ = orc.solve(v0, n, lo, hi, per, "rel_dubins", (0.0, 0.0, 0.0, 1.0), "weno5", 3,
+                        0.8, 0.0, T, "set")
+    ex = np.maximum(np.abs(PS) - T, 0) - 0.5
+    assert metrics.hausdorff_cells(out, ex, per) < 0.05
+    assert np.abs(out - ex)[np.abs(ex) < 0.3].max() < 1e-3
+
+
+def test_dubins4d_heading_and_speed_terms(orc):
+    """V0 = box in (th, v): the control turns at |w| <= 1 and accelerates at
+    |a| <= 0.5, minimising, so the box grows by (w T, a T):
+    V = max(max(|th| - T, 0), max(|v - 2| - T/2, 0)) - 0.5."""
+    n, lo, hi, per = (7, 7, 121, 41), (-1.0, -1.0, -PI, 0.0), (1.0, 1.0, PI, 4.0), \
+        (False, False, True, False)
+    _, _, TH, V = np.meshgrid(*inputs.node_coords(n, lo, hi, per), indexing="ij")
+    v0 = np.ascontiguousarray(np.maximum(np.abs(TH) - 0.5, np.abs(V - 2.0) - 0.5))
+    T = 0.4
+    out, *_ = orc.solve(v0, n, lo, hi, per, "dubins4d", (1.0, 0.5), "weno5", 3, 0.8, 0.0, T,
+                        "set")
+    ex = np.maximum(np.maximum(np.abs(TH) - T, 0) - 0.5, np.maximum(np.abs(V - 2.0) - T / 2, 0) - 0.5)
+    assert metrics.hausdorff_cells(out, ex, per) < 0.6
+    assert np.abs(out - ex)[np.abs(ex) < 0.2].max() < 0.06
