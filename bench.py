@@ -1,0 +1,177 @@
+"""Benchmark: grid-point updates/s of the level-set explicit time step on one
+MI355X.
+
+Workload (one "step" of this benchmark = one whole solve): the relative-Dubins
+pursuit-evasion tube, ve = vp = 5, |we|,|wp| <= 1, grid 101^3 on
+[-6,20]x[-10,10]x[-pi,pi) (psi periodic), V0 = sqrt(x^2+y^2) - 5,
+WENO5 + Lax-Friedrichs + TVD-RK3, CFL 0.8, tube to t = 2.8 (820 RK steps,
+2460 fused stage launches plus the alpha reduction), FP64.  Inputs are resident
+in HBM before the timed region starts.
+
+Prints one JSON line (rank 0).  Also reports the roofline of the dominant
+kernel (the fused WENO5 stage kernel, timed with HIP events on the stream it
+is launched on) and the FP64 CPU oracle timed on the host's cores.
+
+    python bench.py [--steps K] [--warmup W] [--prec fp64|fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-point updates/s (WENO5+LF+RK3) served vs plain; p50/p99 solve latency"
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def weno5_flops_per_node_stage(ndim: int) -> float:
+    """Algorithmic floating-point operations of one stage at one node, counted
+    on the formulas (Sec. 3.3, 4, 5), not on the GPU instruction stream:
+    per axis 6 first differences (6 sub + 6 div) and two WENO5 evaluations of
+    78 operations each (candidates 15, smoothness 33, eps 11, weights 9,
+    normalisation and blend 10); then p-bar 2/axis, LF dissipation 4/axis,
+    the relative-Dubins Hamiltonian 17, the sign 1 and the RK blend (average
+    of the three RK3 stages) 13/3."""
+    per_axis = 12 + 2 * 78
+    return ndim * (per_axis + 2 + 4) + 17 + 1 + 13.0 / 3.0
+
+
+def bytes_per_node_stage(elem: int, tube: bool) -> float:
+    """Algorithmic HBM bytes per node per RK3 stage (average of the three):
+    stage 1 reads V and writes A; stage 2 reads A and V and writes B; stage 3
+    reads B, V (and V0 for a tube) and writes V."""
+    passes = 2 + 3 + (4 if tube else 3)
+    return passes * elem / 3.0
+
+
+def cpu_baseline(p, target_s: float = 15.0):
+    import oracle
+
+    threads = oracle.set_threads(0)
+    v0 = p.v0()
+    alpha, dt, k, _ = oracle.schedule(*p.grid_args(), p.dynamics, p.params, p.cfl, p.t0, p.tf)
+    t = time.perf_counter()
+    oracle.steps(v0, v0, *p.grid_args(), p.dynamics, p.params, p.scheme, p.order, alpha, dt, 1,
+                 mode=p.mode)
+    one = time.perf_counter() - t
+    nsteps = int(max(1, min(k, round(target_s / max(one, 1e-3)))))
+    t = time.perf_counter()
+    oracle.steps(v0, v0, *p.grid_args(), p.dynamics, p.params, p.scheme, p.order, alpha, dt,
+                 nsteps, mode=p.mode)
+    el = time.perf_counter() - t
+    return {"value": p.points * nsteps / el, "unit": "grid-point updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "first %d of the %d RK3 steps of the same 101^3 tube solve "
+                      "(FP64 C oracle, OpenMP over nodes), %.1f s" % (nsteps, k, el)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-steps", type=int, default=40,
+                    help="RK steps timed with HIP events for the kernel roofline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only; multi-GPU runs are not part of this build "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2507_11542_amd import hj, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    p = inputs.rel_dubins_3d()
+    dtype = torch.float64 if args.prec == "fp64" else torch.float32
+    elem = 8 if args.prec == "fp64" else 4
+    stream = torch.cuda.current_stream()
+    v0 = torch.from_numpy(p.v0()).to("cuda", dtype=dtype)
+    out = torch.empty_like(v0)
+    g = hj.Grid.from_problem(p, args.prec)
+    alpha, dt, nsteps = g.schedule(p.t0, p.tf, stream)
+    updates_per_solve = p.points * nsteps
+
+    for _ in range(args.warmup):
+        g.solve(v0, out, p.t0, p.tf, p.mode, stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        g.solve(v0, out, p.t0, p.tf, p.mode, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = updates_per_solve * args.steps / elapsed
+
+    # dominant kernel: the fused stage kernel, 3 launches per RK3 step
+    vk = v0.clone()
+    tt = 0.0
+    for _ in range(3):
+        tt, _ = g.step(vk, v0, tt, p.tf, p.mode, stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.kernel_steps):
+        tt, _ = g.step(vk, v0, tt, p.tf, p.mode, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    launch_s = e0.elapsed_time(e1) / 1e3 / (3 * args.kernel_steps)
+    flops = weno5_flops_per_node_stage(p.ndim) * p.points
+    achieved = flops / launch_s / 1e12
+    peak = FP64_PEAK_TFLOPS if args.prec == "fp64" else FP32_PEAK_TFLOPS
+    hbm_gbs = bytes_per_node_stage(elem, p.mode == "tube") * p.points / launch_s / 1e9
+
+    # error of the timed result against the FP64 oracle at stored samples
+    err = None
+    gold = os.path.join(ROOT, "tests", "golden", "rel_dubins_3d_101_tube_samples.txt")
+    if os.path.exists(gold):
+        data = np.loadtxt(gold)
+        idx = data[:, 0].astype(np.int64)
+        got = out.double().cpu().numpy().ravel()[idx]
+        err = float(np.abs(got - data[:, 1]).max())
+    g.close()
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32",
+        "data": "synthetic (analytic dynamics and signed-distance V0)",
+        "config": {"workload": "rel_dubins_3d 101^3 WENO5+LF+RK3 tube t=2.8, plain solve",
+                   "grid": list(p.n), "rk_steps": nsteps, "dt": dt, "alpha": alpha,
+                   "path": "plain (hj_solve, one solve at a time)"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "stage_kernel<%s,3,WENO5,REL_DUBINS>" % args.prec,
+                     "launch_us": launch_s * 1e6,
+                     "algorithmic_hbm_GBs": hbm_gbs,
+                     "flops_per_node_stage": weno5_flops_per_node_stage(p.ndim)},
+        "error_vs_oracle_fp64": err,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(rec))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,143 @@
+/*
+ * hj.h -- C ABI of libhj, an MI355X (gfx950) implementation of the explicit
+ * time step of the level-set / Hamilton-Jacobi(-Isaacs) method of
+ * arXiv 2507.11542 (LevelSetPy).
+ *
+ * One call of hj_solve advances V_t + H(x, grad V) = 0 (Sec. 1.1, eq. ivp;
+ * Sec. 4, eq. HJEquation) from V(t0) = V0 to tf on a dense Cartesian grid:
+ * upwinded one-sided derivatives per axis (Sec. 3.1 first order, Sec. 3.2 ENO2,
+ * Sec. 3.3 WENO5), the Lax-Friedrichs numerical Hamiltonian with dissipation
+ * alpha_i = max over the grid of |dH/dp_i| (Sec. 4, LF equation), the CFL step
+ * (Sec. 4), TVD Runge-Kutta stages (Sec. 5, odeCFL3 listing) and, for a
+ * backward reachable tube, V <- min(V, V0) after every step (Sec. 6.1).
+ *
+ * Conventions shared by every call:
+ *  - Arrays are C-order (last axis fastest), contiguous, one element per grid
+ *    node, element type double (HJ_FP64) or float (HJ_FP32) as chosen at
+ *    hj_grid_create.  The paper stores column-major (Sec. 2.1); the layout
+ *    carries no meaning beyond the index order.
+ *  - Pointers named V* are DEVICE pointers owned by the caller (for example
+ *    torch tensors).  Other pointers are host pointers.
+ *  - hip_stream is a hipStream_t (NULL = the null stream).  Calls that take a
+ *    stream only enqueue work on it and return; the caller synchronises.
+ *    hj_solve reads alpha back once per solve (a short wait on the stream
+ *    before the step launches are enqueued).
+ *  - Every call returns HJ_OK or a negative hj_status; hj_last_error() gives a
+ *    message for the calling thread.  A handle is not thread-safe; separate
+ *    handles are independent.
+ */
+#ifndef HJ_H_
+#define HJ_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hj_grid_s *hj_grid_t;
+
+typedef enum {
+    HJ_OK = 0,
+    HJ_E_ARG = -1,         /* invalid argument (message says which) */
+    HJ_E_OOM = -2,         /* device or host allocation failed */
+    HJ_E_DEVICE = -3,      /* a HIP call failed */
+    HJ_E_STATE = -4,       /* call order violated (e.g. no dynamics set) */
+    HJ_E_NUMERIC = -5,     /* non-finite value detected where checked */
+    HJ_E_UNSUPPORTED = -6  /* valid but not built (e.g. dynamics/ndim pair) */
+} hj_status;
+
+/* HJ_FP32 stores and computes V in float; alpha, dt and t stay double. */
+typedef enum { HJ_FP64 = 0, HJ_FP32 = 1 } hj_precision;
+
+/* HJ_SET: the reachable set V(tf).  HJ_TUBE: the tube, V <- min(V, V0) after
+ * every full step (Sec. 6.1, backward reachable tube). */
+typedef enum { HJ_SET = 0, HJ_TUBE = 1 } hj_mode;
+
+/* One-sided derivative approximations (Sec. 3): first order (Sec. 3.1, halo
+ * 1), ENO2 (Sec. 3.2, halo 2), WENO5 (Sec. 3.3, halo 3). */
+typedef enum { HJ_UPWIND1 = 1, HJ_ENO2 = 2, HJ_WENO5 = 5 } hj_space;
+
+/* TVD Runge-Kutta order (Sec. 5): forward Euler, Shu-Osher RK2, RK3. */
+typedef enum { HJ_RK1 = 1, HJ_RK2 = 2, HJ_RK3 = 3 } hj_time;
+
+/* Compiled dynamics, sign convention V_t + H = 0, H = -opt_{u,d} p.f(x,u,d).
+ * params (in order) and dimension:
+ *   HJ_DYN_TRANSLATION       any ndim   b[0..ndim-1]        x' = b,         H = -b.p
+ *   HJ_DYN_BALL              any ndim   s                   x' = s u, |u|<=1, H = s|p|
+ *   HJ_DYN_DOUBLE_INTEGRATOR ndim 2     umax                x1' = x2, x2' = u, |u|<=umax,
+ *                                                           control minimises
+ *   HJ_DYN_REL_DUBINS        ndim 3     ve, vp, we, wp      (x, y, psi) relative Dubins
+ *                                       pursuit-evasion; evader (|we|) maximises,
+ *                                       pursuer (|wp|) minimises
+ *   HJ_DYN_DUBINS4D          ndim 4     wmax, amax          (x, y, th, v) Dubins car with
+ *                                       speed state, control minimises */
+typedef enum {
+    HJ_DYN_TRANSLATION = 0,
+    HJ_DYN_BALL = 1,
+    HJ_DYN_DOUBLE_INTEGRATOR = 2,
+    HJ_DYN_REL_DUBINS = 3,
+    HJ_DYN_DUBINS4D = 4
+} hj_dyn;
+
+/* Sec. 2.1 (createGrid(min, max, N, pdim)).  ndim in [1, 4]; N[i] nodes on
+ * axis i in [lo[i], hi[i]]; bit i of periodic_mask makes axis i periodic.  A
+ * bounded axis has both ends as nodes, dx = (hi-lo)/(N-1); a periodic axis
+ * excludes hi, dx = (hi-lo)/N.  Bounded axes take linearly extrapolated ghost
+ * values.  Needs N[i] >= 7 (the widest stencil), lo < hi, prod(N) < 2^31.
+ * Allocates the per-axis coordinate tables on the current HIP device; the
+ * handle owns them and its stage buffers until hj_grid_destroy. */
+hj_status hj_grid_create(int ndim, const int64_t *N, const double *lo, const double *hi,
+                         uint32_t periodic_mask, hj_precision prec, hj_grid_t *out);
+
+/* Sec. 6.1 / eq. ham_def: choose the Hamiltonian (see hj_dyn).  params is a
+ * host array of nparams doubles; HJ_E_ARG on a wrong count, HJ_E_UNSUPPORTED
+ * when the dynamics needs another ndim. */
+hj_status hj_set_dynamics(hj_grid_t g, hj_dyn kind, const double *params, int nparams);
+
+/* Sec. 3-5: derivative scheme, RK order and CFL number (0 < cfl <= 1).  The
+ * default is WENO5, RK3, 0.8. */
+hj_status hj_set_scheme(hj_grid_t g, hj_space space, hj_time time, double cfl);
+
+/* Sec. 5 time loop over [t0, tf] (odeCFL3): alpha is max-reduced on the GPU,
+ * dt = cfl / sum_i alpha_i/dx_i, steps of min(dt, tf - t) until
+ * tf - t < 100*2^-52*(tf - t0).  V0 and V_out are device arrays of prod(N)
+ * elements; V_out receives V(tf) and must not overlap V0.  t0 == tf copies
+ * V0.  HJ_E_ARG on NULL pointers, overlap, tf < t0 or non-finite times. */
+hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double tf,
+                   hj_mode mode, void *hip_stream);
+
+/* One full TVD-RK step in place on V (device), of size min(dt, tf - *t),
+ * then the tube update against V0 when mode is HJ_TUBE (V0 may be NULL for
+ * HJ_SET).  *t advances by the step (FP64, host); *dt_used receives it
+ * (may be NULL).  alpha is reduced on the first call and cached.  Resuming a
+ * solve from (V, t) is a sequence of hj_step calls. */
+hj_status hj_step(hj_grid_t g, void *V, const void *V0, double *t, double tf,
+                  hj_mode mode, double *dt_used, void *hip_stream);
+
+/* Sec. 4: L(V) = -Hhat(p-, p+) at every node (the semi-discrete right-hand
+ * side of one stage) into L_out (device, same element type).  Runs the alpha
+ * reduction first if no alpha is cached. */
+hj_status hj_rhs(hj_grid_t g, const void *V, void *L_out, void *hip_stream);
+
+/* Sec. 4 dissipation and CFL bound: runs the GPU max-reduction of |dH/dp_i|
+ * over all nodes (synchronising the stream), caches it, and returns alpha
+ * (ndim doubles), dt and the step count for [t0, tf].  Any output may be NULL. */
+hj_status hj_get_schedule(hj_grid_t g, double t0, double tf, double *alpha, double *dt,
+                          int64_t *n_steps, void *hip_stream);
+
+/* Frees the handle, its tables and stage buffers (after the device is idle
+ * for this handle's work).  NULL is accepted. */
+hj_status hj_grid_destroy(hj_grid_t g);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *hj_last_error(void);
+
+/* Library version string. */
+const char *hj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJ_H_ */

@@ -1,0 +1,500 @@
+// libhj host runtime: the C ABI of include/hj.h.
+//
+// A handle holds the grid geometry (Sec. 2.1), the per-axis coordinate and
+// trigonometric tables (computed once with the host libm), the compiled
+// dynamics and scheme choice, and the device buffers of the TVD-RK stages.
+// hj_solve reduces alpha on the GPU, reads it back once, fixes the whole step
+// schedule on the host in FP64 (Sec. 5 time loop) and enqueues every stage
+// launch on the caller's stream without further synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hj.h"
+#include "hj_internal.h"
+
+using namespace hj;
+
+namespace {
+
+thread_local std::string g_err;
+
+hj_status fail(hj_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+hj_status hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? HJ_E_OOM : HJ_E_DEVICE;
+}
+
+#define HJ_HIP(call, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, (what));   \
+    } while (0)
+
+int halo_of(int space) { return space == HJ_UPWIND1 ? 1 : (space == HJ_ENO2 ? 2 : 3); }
+
+// Testing hook: HJ_FAULT_OOM=1 makes every device allocation of the library
+// report HJ_E_OOM without calling the allocator.
+bool fault_oom()
+{
+    const char *s = std::getenv("HJ_FAULT_OOM");
+    return s && s[0] == '1';
+}
+
+hj_status dev_alloc(void **p, size_t bytes, const char *what)
+{
+    if (fault_oom()) return fail(HJ_E_OOM, std::string(what) + ": injected allocation failure");
+    HJ_HIP(hipMalloc(p, bytes), what);
+    return HJ_OK;
+}
+
+}  // namespace
+
+struct hj_grid_s {
+    int nd = 0;
+    int64_t n[kMaxDim] = {1, 1, 1, 1};
+    double lo[kMaxDim] = {0, 0, 0, 0}, hi[kMaxDim] = {0, 0, 0, 0}, dx[kMaxDim] = {1, 1, 1, 1};
+    uint32_t pmask = 0;
+    hj_precision prec = HJ_FP64;
+    int64_t total = 0;
+    uint32_t stride[kMaxDim] = {0, 0, 0, 0};
+    uint32_t tab_off[kMaxDim] = {0, 0, 0, 0};
+    int device = 0;
+
+    int dyn = -1;
+    double prm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+    int space = HJ_WENO5;
+    int order = 3;
+    double cfl = 0.8;
+
+    double *tab64 = nullptr;   // device, FP64 tables (alpha and FP64 stages)
+    float *tab32 = nullptr;    // device, FP32 tables (FP32 stages)
+    void *bufA = nullptr;      // stage buffers
+    void *bufB = nullptr;
+    double *partial = nullptr; // alpha pass-1 partial maxima
+    double *alpha_dev = nullptr;
+    double *alpha_host = nullptr;  // pinned
+    bool alpha_valid = false;
+    double alpha[kMaxDim] = {0, 0, 0, 0};
+
+    size_t elem() const { return prec == HJ_FP64 ? sizeof(double) : sizeof(float); }
+    size_t bytes() const { return size_t(total) * elem(); }
+};
+
+namespace {
+
+hj_status use_device(hj_grid_t g)
+{
+    HJ_HIP(hipSetDevice(g->device), "hipSetDevice");
+    return HJ_OK;
+}
+
+hj_status ensure_buffers(hj_grid_t g, bool need_b)
+{
+    hj_status s;
+    if (!g->bufA && (s = dev_alloc(&g->bufA, g->bytes(), "stage buffer A")) != HJ_OK) return s;
+    if (need_b && !g->bufB && (s = dev_alloc(&g->bufB, g->bytes(), "stage buffer B")) != HJ_OK)
+        return s;
+    return HJ_OK;
+}
+
+hj_status check_ready(hj_grid_t g)
+{
+    if (!g) return fail(HJ_E_ARG, "null grid handle");
+    if (g->dyn < 0) return fail(HJ_E_STATE, "hj_set_dynamics has not been called");
+    const int w = halo_of(g->space);
+    for (int d = 0; d < g->nd; ++d)
+        if (g->n[d] < 2 * w + 1)
+            return fail(HJ_E_ARG, "axis " + std::to_string(d) + " has " +
+                                      std::to_string(g->n[d]) + " nodes; the scheme needs >= " +
+                                      std::to_string(2 * w + 1));
+    return HJ_OK;
+}
+
+// GPU max-reduction of the speed bounds (Sec. 4), read back through pinned
+// memory: the one synchronisation of a solve.
+hj_status compute_alpha(hj_grid_t g, hipStream_t s)
+{
+    AlphaArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tab = g->tab64;
+    for (int d = 0; d < kMaxDim; ++d) {
+        a.n[d] = uint32_t(g->n[d]);
+        a.tab_off[d] = g->tab_off[d];
+    }
+    a.total = uint32_t(g->total);
+    for (int k = 0; k < 8; ++k) a.prm[k] = g->prm[k];
+    hipError_t e = launch_alpha(g->nd, g->dyn, a, g->partial, g->alpha_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "alpha reduction launch");
+    HJ_HIP(hipMemcpyAsync(g->alpha_host, g->alpha_dev, sizeof(double) * g->nd,
+                          hipMemcpyDeviceToHost, s),
+           "alpha read-back");
+    HJ_HIP(hipStreamSynchronize(s), "alpha synchronise");
+    for (int d = 0; d < g->nd; ++d) g->alpha[d] = g->alpha_host[d];
+    g->alpha_valid = true;
+    return HJ_OK;
+}
+
+// Sec. 4 CFL bound: dt * sum_d alpha_d / dx_d = cfl.
+double cfl_dt(hj_grid_t g)
+{
+    double rate = 0.0;
+    for (int d = 0; d < g->nd; ++d) rate += g->alpha[d] / g->dx[d];
+    return rate > 0.0 ? g->cfl / rate : INFINITY;
+}
+
+constexpr double kEpsT = 100.0 * 2.220446049250313e-16;
+
+// Sec. 5 time loop: step sizes min(dt, tf - t) until tf - t < eps (tf - t0).
+void schedule(double dt, double t0, double tf, std::vector<double> *hs)
+{
+    double t = t0;
+    if (!(tf > t0)) return;
+    while (tf - t >= kEpsT * (tf - t0)) {
+        const double h = dt < tf - t ? dt : tf - t;
+        hs->push_back(h);
+        t = t + h;
+    }
+}
+
+template <typename T>
+StageArgs<T> base_args(hj_grid_t g)
+{
+    StageArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.tab = (const T *)(g->prec == HJ_FP64 ? (const void *)g->tab64 : (const void *)g->tab32);
+    for (int d = 0; d < kMaxDim; ++d) {
+        a.n[d] = uint32_t(g->n[d]);
+        a.stride[d] = g->stride[d];
+        a.tab_off[d] = g->tab_off[d];
+        a.dx[d] = T(g->dx[d]);
+        a.inv_dx[d] = T(1.0 / g->dx[d]);
+        a.alpha[d] = T(g->alpha[d]);
+    }
+    a.total = uint32_t(g->total);
+    a.periodic = g->pmask;
+    for (int k = 0; k < 8; ++k) a.prm[k] = T(g->prm[k]);
+    return a;
+}
+
+template <typename T>
+hj_status launch(hj_grid_t g, const StageArgs<T> &a, hipStream_t s);
+
+template <>
+hj_status launch<double>(hj_grid_t g, const StageArgs<double> &a, hipStream_t s)
+{
+    hipError_t e = launch_stage_f64(g->nd, g->space, g->dyn, a, s);
+    if (e != hipSuccess) return hip_fail(e, "stage launch (fp64)");
+    return HJ_OK;
+}
+
+template <>
+hj_status launch<float>(hj_grid_t g, const StageArgs<float> &a, hipStream_t s)
+{
+    hipError_t e = launch_stage_f32(g->nd, g->space, g->dyn, a, s);
+    if (e != hipSuccess) return hip_fail(e, "stage launch (fp32)");
+    return HJ_OK;
+}
+
+// One stage: out = combine(vs, vb, L(vs)), then min with v0 when tube.
+template <typename T>
+hj_status stage(hj_grid_t g, const void *vs, const void *vb, const void *v0, void *out,
+                Combine c, double dt, double wb, double w2, double den, bool tube,
+                hipStream_t s)
+{
+    StageArgs<T> a = base_args<T>(g);
+    a.vs = (const T *)vs;
+    a.vb = (const T *)vb;
+    a.v0 = (const T *)v0;
+    a.out = (T *)out;
+    a.combine = c;
+    a.dt = T(dt);
+    a.wb = T(wb);
+    a.w2 = T(w2);
+    a.den = T(den);
+    a.tube = tube ? 1 : 0;
+    return launch<T>(g, a, s);
+}
+
+// One TVD-RK step of size h in place on v (Sec. 5, odeCFL listing):
+//   RK1  v <- v + h L(v)
+//   RK2  A <- v + h L(v);  v <- (v + (A + h L(A))) / 2
+//   RK3  A <- v + h L(v);  B <- (3v + (A + h L(A))) / 4;  v <- (v + 2(B + h L(B))) / 3
+// followed by the tube minimum with v0 (fused in the last stage).
+template <typename T>
+hj_status rk_step(hj_grid_t g, void *v, const void *v0, bool tube, double h, hipStream_t s)
+{
+    hj_status st;
+    if (g->order == 1) {
+        if ((st = stage<T>(g, v, nullptr, v0, g->bufA, kEuler, h, 0, 0, 1, tube, s)) != HJ_OK)
+            return st;
+        HJ_HIP(hipMemcpyAsync(v, g->bufA, g->bytes(), hipMemcpyDeviceToDevice, s),
+               "RK1 copy-back");
+        return HJ_OK;
+    }
+    if ((st = stage<T>(g, v, nullptr, nullptr, g->bufA, kEuler, h, 0, 0, 1, false, s)) != HJ_OK)
+        return st;
+    if (g->order == 2)
+        return stage<T>(g, g->bufA, v, v0, v, kBlend, h, 1.0, 1.0, 2.0, tube, s);
+    if ((st = stage<T>(g, g->bufA, v, nullptr, g->bufB, kBlend, h, 3.0, 1.0, 4.0, false, s)) !=
+        HJ_OK)
+        return st;
+    return stage<T>(g, g->bufB, v, v0, v, kBlend, h, 1.0, 2.0, 3.0, tube, s);
+}
+
+template <typename T>
+hj_status run_steps(hj_grid_t g, void *v, const void *v0, bool tube,
+                    const std::vector<double> &hs, hipStream_t s)
+{
+    for (double h : hs) {
+        hj_status st = rk_step<T>(g, v, v0, tube, h, s);
+        if (st != HJ_OK) return st;
+    }
+    return HJ_OK;
+}
+
+bool overlap(const void *a, const void *b, size_t bytes)
+{
+    const uintptr_t x = uintptr_t(a), y = uintptr_t(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hj_last_error(void) { return g_err.c_str(); }
+
+const char *hj_version(void) { return "libhj 0.1 (gfx950)"; }
+
+hj_status hj_grid_create(int ndim, const int64_t *N, const double *lo, const double *hi,
+                         uint32_t periodic_mask, hj_precision prec, hj_grid_t *out)
+{
+    if (!out) return fail(HJ_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (ndim < 1 || ndim > kMaxDim) return fail(HJ_E_ARG, "ndim must be in [1, 4]");
+    if (!N || !lo || !hi) return fail(HJ_E_ARG, "N, lo and hi must be non-NULL");
+    if (prec != HJ_FP64 && prec != HJ_FP32) return fail(HJ_E_ARG, "unknown precision");
+    if (periodic_mask >> ndim) return fail(HJ_E_ARG, "periodic_mask names an axis >= ndim");
+    int64_t total = 1;
+    for (int d = 0; d < ndim; ++d) {
+        if (N[d] < 3) return fail(HJ_E_ARG, "every axis needs at least 3 nodes");
+        if (!(std::isfinite(lo[d]) && std::isfinite(hi[d]) && lo[d] < hi[d]))
+            return fail(HJ_E_ARG, "need finite lo < hi on every axis");
+        total *= N[d];
+        if (total >= (int64_t(1) << 31)) return fail(HJ_E_ARG, "grid exceeds 2^31 nodes");
+    }
+    hj_grid_s *g = new (std::nothrow) hj_grid_s();
+    if (!g) return fail(HJ_E_OOM, "host allocation of the handle");
+    g->nd = ndim;
+    g->prec = prec;
+    g->pmask = periodic_mask;
+    g->total = total;
+    uint32_t off = 0;
+    for (int d = 0; d < ndim; ++d) {
+        g->n[d] = N[d];
+        g->lo[d] = lo[d];
+        g->hi[d] = hi[d];
+        const bool per = (periodic_mask >> d) & 1u;
+        g->dx[d] = per ? (hi[d] - lo[d]) / double(N[d]) : (hi[d] - lo[d]) / double(N[d] - 1);
+        g->tab_off[d] = off;
+        off += uint32_t(3 * N[d]);
+    }
+    uint32_t st = 1;
+    for (int d = ndim - 1; d >= 0; --d) {
+        g->stride[d] = st;
+        st *= uint32_t(g->n[d]);
+    }
+    // coordinate tables x_k = lo + k dx, cos x_k, sin x_k (host libm, FP64)
+    std::vector<double> t64(off);
+    for (int d = 0; d < ndim; ++d)
+        for (int64_t k = 0; k < N[d]; ++k) {
+            const double x = lo[d] + double(k) * g->dx[d];
+            t64[g->tab_off[d] + k] = x;
+            t64[g->tab_off[d] + N[d] + k] = std::cos(x);
+            t64[g->tab_off[d] + 2 * N[d] + k] = std::sin(x);
+        }
+    hj_status s = HJ_OK;
+    hipError_t e = hipGetDevice(&g->device);
+    if (e != hipSuccess) s = hip_fail(e, "hipGetDevice");
+    if (s == HJ_OK) s = dev_alloc((void **)&g->tab64, sizeof(double) * off, "coordinate table");
+    if (s == HJ_OK) {
+        e = hipMemcpy(g->tab64, t64.data(), sizeof(double) * off, hipMemcpyHostToDevice);
+        if (e != hipSuccess) s = hip_fail(e, "coordinate table upload");
+    }
+    if (s == HJ_OK && prec == HJ_FP32) {
+        std::vector<float> t32(t64.begin(), t64.end());
+        s = dev_alloc((void **)&g->tab32, sizeof(float) * off, "coordinate table (fp32)");
+        if (s == HJ_OK) {
+            e = hipMemcpy(g->tab32, t32.data(), sizeof(float) * off, hipMemcpyHostToDevice);
+            if (e != hipSuccess) s = hip_fail(e, "coordinate table upload (fp32)");
+        }
+    }
+    if (s == HJ_OK)
+        s = dev_alloc((void **)&g->partial,
+                      sizeof(double) * alpha_blocks(uint32_t(total)) * ndim, "alpha partials");
+    if (s == HJ_OK) s = dev_alloc((void **)&g->alpha_dev, sizeof(double) * kMaxDim, "alpha");
+    if (s == HJ_OK) {
+        e = hipHostMalloc((void **)&g->alpha_host, sizeof(double) * kMaxDim, 0);
+        if (e != hipSuccess) s = hip_fail(e, "pinned alpha");
+    }
+    if (s != HJ_OK) {
+        hj_grid_destroy(g);
+        return s;
+    }
+    *out = g;
+    return HJ_OK;
+}
+
+hj_status hj_set_dynamics(hj_grid_t g, hj_dyn kind, const double *params, int nparams)
+{
+    if (!g) return fail(HJ_E_ARG, "null grid handle");
+    int want = -1, nd_need = 0;
+    switch (kind) {
+    case HJ_DYN_TRANSLATION: want = g->nd; break;
+    case HJ_DYN_BALL: want = 1; break;
+    case HJ_DYN_DOUBLE_INTEGRATOR: want = 1; nd_need = 2; break;
+    case HJ_DYN_REL_DUBINS: want = 4; nd_need = 3; break;
+    case HJ_DYN_DUBINS4D: want = 2; nd_need = 4; break;
+    default: return fail(HJ_E_ARG, "unknown dynamics");
+    }
+    if (nd_need && g->nd != nd_need)
+        return fail(HJ_E_UNSUPPORTED, "these dynamics need ndim = " + std::to_string(nd_need));
+    if (nparams != want || (want > 0 && !params))
+        return fail(HJ_E_ARG, "dynamics expects " + std::to_string(want) + " parameters");
+    for (int k = 0; k < nparams; ++k)
+        if (!std::isfinite(params[k])) return fail(HJ_E_ARG, "non-finite dynamics parameter");
+    g->dyn = kind;
+    for (int k = 0; k < 8; ++k) g->prm[k] = k < nparams ? params[k] : 0.0;
+    g->alpha_valid = false;
+    return HJ_OK;
+}
+
+hj_status hj_set_scheme(hj_grid_t g, hj_space space, hj_time time, double cfl)
+{
+    if (!g) return fail(HJ_E_ARG, "null grid handle");
+    if (space != HJ_UPWIND1 && space != HJ_ENO2 && space != HJ_WENO5)
+        return fail(HJ_E_ARG, "unknown spatial scheme");
+    if (time != HJ_RK1 && time != HJ_RK2 && time != HJ_RK3)
+        return fail(HJ_E_ARG, "unknown RK order");
+    if (!(cfl > 0.0 && cfl <= 1.0)) return fail(HJ_E_ARG, "cfl must be in (0, 1]");
+    g->space = space;
+    g->order = time;
+    g->cfl = cfl;
+    return HJ_OK;
+}
+
+hj_status hj_get_schedule(hj_grid_t g, double t0, double tf, double *alpha, double *dt,
+                          int64_t *n_steps, void *hip_stream)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (!(std::isfinite(t0) && std::isfinite(tf) && tf >= t0))
+        return fail(HJ_E_ARG, "need finite t0 <= tf");
+    if ((s = use_device(g)) != HJ_OK) return s;
+    if ((s = compute_alpha(g, (hipStream_t)hip_stream)) != HJ_OK) return s;
+    const double d = cfl_dt(g);
+    std::vector<double> hs;
+    schedule(d, t0, tf, &hs);
+    if (alpha)
+        for (int k = 0; k < g->nd; ++k) alpha[k] = g->alpha[k];
+    if (dt) *dt = d;
+    if (n_steps) *n_steps = int64_t(hs.size());
+    return HJ_OK;
+}
+
+hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double tf, hj_mode mode,
+                   void *hip_stream)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (!V0 || !V_out) return fail(HJ_E_ARG, "V0 and V_out must be non-NULL");
+    if (mode != HJ_SET && mode != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
+    if (!(std::isfinite(t0) && std::isfinite(tf) && tf >= t0))
+        return fail(HJ_E_ARG, "need finite t0 <= tf");
+    if (overlap(V0, V_out, g->bytes())) return fail(HJ_E_ARG, "V_out overlaps V0");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = use_device(g)) != HJ_OK) return s;
+    if ((s = ensure_buffers(g, g->order == 3)) != HJ_OK) return s;
+    if ((s = compute_alpha(g, st)) != HJ_OK) return s;
+    std::vector<double> hs;
+    schedule(cfl_dt(g), t0, tf, &hs);
+    HJ_HIP(hipMemcpyAsync(V_out, V0, g->bytes(), hipMemcpyDeviceToDevice, st), "copy V0");
+    const bool tube = mode == HJ_TUBE;
+    if (g->prec == HJ_FP64) return run_steps<double>(g, V_out, V0, tube, hs, st);
+    return run_steps<float>(g, V_out, V0, tube, hs, st);
+}
+
+hj_status hj_step(hj_grid_t g, void *V, const void *V0, double *t, double tf, hj_mode mode,
+                  double *dt_used, void *hip_stream)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (!V || !t) return fail(HJ_E_ARG, "V and t must be non-NULL");
+    if (mode != HJ_SET && mode != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
+    if (mode == HJ_TUBE && !V0) return fail(HJ_E_ARG, "tube mode needs V0");
+    if (!(std::isfinite(*t) && std::isfinite(tf))) return fail(HJ_E_ARG, "non-finite time");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = use_device(g)) != HJ_OK) return s;
+    if ((s = ensure_buffers(g, g->order == 3)) != HJ_OK) return s;
+    if (!g->alpha_valid && (s = compute_alpha(g, st)) != HJ_OK) return s;
+    const double dt = cfl_dt(g);
+    if (!(tf > *t)) {
+        if (dt_used) *dt_used = 0.0;
+        return HJ_OK;
+    }
+    const double h = dt < tf - *t ? dt : tf - *t;
+    if (g->prec == HJ_FP64)
+        s = rk_step<double>(g, V, V0, mode == HJ_TUBE, h, st);
+    else
+        s = rk_step<float>(g, V, V0, mode == HJ_TUBE, h, st);
+    if (s != HJ_OK) return s;
+    *t = *t + h;
+    if (dt_used) *dt_used = h;
+    return HJ_OK;
+}
+
+hj_status hj_rhs(hj_grid_t g, const void *V, void *L_out, void *hip_stream)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (!V || !L_out) return fail(HJ_E_ARG, "V and L_out must be non-NULL");
+    if (overlap(V, L_out, g->bytes())) return fail(HJ_E_ARG, "L_out overlaps V");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = use_device(g)) != HJ_OK) return s;
+    if (!g->alpha_valid && (s = compute_alpha(g, st)) != HJ_OK) return s;
+    if (g->prec == HJ_FP64)
+        return stage<double>(g, V, nullptr, nullptr, L_out, kRhs, 0, 0, 0, 1, false, st);
+    return stage<float>(g, V, nullptr, nullptr, L_out, kRhs, 0, 0, 0, 1, false, st);
+}
+
+hj_status hj_grid_destroy(hj_grid_t g)
+{
+    if (!g) return HJ_OK;
+    (void)hipSetDevice(g->device);
+    if (g->tab64) (void)hipFree(g->tab64);
+    if (g->tab32) (void)hipFree(g->tab32);
+    if (g->bufA) (void)hipFree(g->bufA);
+    if (g->bufB) (void)hipFree(g->bufB);
+    if (g->partial) (void)hipFree(g->partial);
+    if (g->alpha_dev) (void)hipFree(g->alpha_dev);
+    if (g->alpha_host) (void)hipHostFree(g->alpha_host);
+    delete g;
+    return HJ_OK;
+}
+
+}  // extern "C"

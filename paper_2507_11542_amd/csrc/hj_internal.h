@@ -1,0 +1,62 @@
+// Internal interface between the libhj host runtime (hj_api.cpp) and the
+// gfx950 kernels (hj_stage.hip, hj_alpha.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hj {
+
+constexpr int kMaxDim = 4;
+
+enum Space { kUpwind1 = 1, kEno2 = 2, kWeno5 = 5 };
+enum Dyn { kTranslation = 0, kBall = 1, kDoubleIntegrator = 2, kRelDubins = 3, kDubins4D = 4 };
+
+// How a stage kernel combines the right-hand side L(Vs) with its inputs:
+//   kRhs      out = L(Vs)
+//   kEuler    out = Vs + dt L(Vs)
+//   kBlend    out = (wb Vb + w2 (Vs + dt L(Vs))) / den
+enum Combine { kRhs = 0, kEuler = 1, kBlend = 2 };
+
+// Everything one stage launch needs, by value (kernel argument).
+template <typename T>
+struct StageArgs {
+    const T *vs;      // stage input, read with the stencil
+    const T *vb;      // RK base, read at the node only (kBlend)
+    const T *v0;      // tube target, read at the node only (tube != 0)
+    T *out;           // may alias vb (each node reads vb then writes out)
+    const T *tab;     // per-axis [x(n) | cos x(n) | sin x(n)] blocks
+    uint32_t n[kMaxDim];
+    uint32_t stride[kMaxDim];
+    uint32_t tab_off[kMaxDim];
+    uint32_t total;
+    uint32_t periodic;  // bit d: axis d periodic
+    T dx[kMaxDim];
+    T inv_dx[kMaxDim];
+    T alpha[kMaxDim];
+    T prm[8];
+    T dt, wb, w2, den;
+    int combine;
+    int tube;
+};
+
+struct AlphaArgs {
+    const double *tab;
+    uint32_t n[kMaxDim];
+    uint32_t tab_off[kMaxDim];
+    uint32_t total;
+    double prm[8];
+};
+
+// Launchers (defined in the .hip files).  Return hipSuccess or the launch error.
+hipError_t launch_stage_f64(int ndim, int space, int dyn, const StageArgs<double> &a,
+                            hipStream_t s);
+hipError_t launch_stage_f32(int ndim, int space, int dyn, const StageArgs<float> &a,
+                            hipStream_t s);
+// Two-pass max reduction of the per-node bounds |dH/dp_d| into alpha[0..ndim).
+// partial must hold alpha_blocks(total) * ndim doubles.
+uint32_t alpha_blocks(uint32_t total);
+hipError_t launch_alpha(int ndim, int dyn, const AlphaArgs &a, double *partial, double *alpha,
+                        hipStream_t s);
+
+}  // namespace hj

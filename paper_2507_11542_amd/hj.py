@@ -1,0 +1,212 @@
+"""Python binding of libhj (include/hj.h): the same entry points, argument
+marshalling only.  Every step of a solve runs in the gfx950 kernels of
+libhj.so; there is no CPU fallback: importing this module without the built
+library raises.
+
+Device arrays are passed as torch CUDA(HIP) tensors or raw integer device
+pointers; streams as torch.cuda.Stream or raw hipStream_t integers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhj.so")
+
+# enum values of include/hj.h
+HJ_OK, HJ_E_ARG, HJ_E_OOM, HJ_E_DEVICE, HJ_E_STATE, HJ_E_NUMERIC, HJ_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+HJ_FP64, HJ_FP32 = 0, 1
+HJ_SET, HJ_TUBE = 0, 1
+HJ_UPWIND1, HJ_ENO2, HJ_WENO5 = 1, 2, 5
+HJ_RK1, HJ_RK2, HJ_RK3 = 1, 2, 3
+HJ_DYN_TRANSLATION, HJ_DYN_BALL, HJ_DYN_DOUBLE_INTEGRATOR, HJ_DYN_REL_DUBINS, \
+    HJ_DYN_DUBINS4D = 0, 1, 2, 3, 4
+
+SPACE = {"upwind1": HJ_UPWIND1, "eno2": HJ_ENO2, "weno5": HJ_WENO5}
+DYN = {"translation": HJ_DYN_TRANSLATION, "ball": HJ_DYN_BALL,
+       "double_integrator": HJ_DYN_DOUBLE_INTEGRATOR, "rel_dubins": HJ_DYN_REL_DUBINS,
+       "dubins4d": HJ_DYN_DUBINS4D}
+MODE = {"set": HJ_SET, "tube": HJ_TUBE}
+PREC = {"fp64": HJ_FP64, "fp32": HJ_FP32}
+
+STATUS_NAMES = {HJ_OK: "HJ_OK", HJ_E_ARG: "HJ_E_ARG", HJ_E_OOM: "HJ_E_OOM",
+                HJ_E_DEVICE: "HJ_E_DEVICE", HJ_E_STATE: "HJ_E_STATE",
+                HJ_E_NUMERIC: "HJ_E_NUMERIC", HJ_E_UNSUPPORTED: "HJ_E_UNSUPPORTED"}
+
+
+class HJError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhj.so is not built (run paper_2507_11542_amd.build_lib); "
+                          "there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, U, I64 = (ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint32,
+                       ctypes.c_int64)
+    PD = ctypes.POINTER(ctypes.c_double)
+    PI64 = ctypes.POINTER(ctypes.c_int64)
+    lib.hj_grid_create.argtypes = [I, PI64, PD, PD, U, I, ctypes.POINTER(P)]
+    lib.hj_set_dynamics.argtypes = [P, I, PD, I]
+    lib.hj_set_scheme.argtypes = [P, I, I, D]
+    lib.hj_solve.argtypes = [P, P, P, D, D, I, P]
+    lib.hj_step.argtypes = [P, P, P, PD, D, I, PD, P]
+    lib.hj_rhs.argtypes = [P, P, P, P]
+    lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
+    lib.hj_grid_destroy.argtypes = [P]
+    for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
+                 "hj_rhs", "hj_get_schedule", "hj_grid_destroy"):
+        getattr(lib, name).restype = I
+    lib.hj_last_error.argtypes = []
+    lib.hj_last_error.restype = ctypes.c_char_p
+    lib.hj_version.argtypes = []
+    lib.hj_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def hj_last_error() -> str:
+    return _lib.hj_last_error().decode()
+
+
+def hj_version() -> str:
+    return _lib.hj_version().decode()
+
+
+def _check(status: int):
+    if status != HJ_OK:
+        raise HJError(status, hj_last_error())
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _darr(vals: Sequence[float]):
+    return (ctypes.c_double * max(1, len(vals)))(*vals)
+
+
+def hj_grid_create(N: Sequence[int], lo: Sequence[float], hi: Sequence[float],
+                   periodic_mask: int = 0, prec: int = HJ_FP64) -> ctypes.c_void_p:
+    nd = len(N)
+    n = (ctypes.c_int64 * nd)(*[int(v) for v in N])
+    h = ctypes.c_void_p()
+    _check(_lib.hj_grid_create(nd, n, _darr(lo), _darr(hi), int(periodic_mask), int(prec),
+                               ctypes.byref(h)))
+    return h
+
+
+def hj_set_dynamics(g, kind: int, params: Sequence[float]):
+    _check(_lib.hj_set_dynamics(g, int(kind), _darr(list(params)), len(params)))
+
+
+def hj_set_scheme(g, space: int = HJ_WENO5, time: int = HJ_RK3, cfl: float = 0.8):
+    _check(_lib.hj_set_scheme(g, int(space), int(time), float(cfl)))
+
+
+def hj_solve(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, stream=None):
+    _check(_lib.hj_solve(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
+                         _stream(stream)))
+
+
+def hj_step(g, V, V0, t: float, tf: float, mode: int = HJ_SET, stream=None
+            ) -> Tuple[float, float]:
+    tt = ctypes.c_double(t)
+    dt = ctypes.c_double(0.0)
+    _check(_lib.hj_step(g, _ptr(V), _ptr(V0), ctypes.byref(tt), float(tf), int(mode),
+                        ctypes.byref(dt), _stream(stream)))
+    return tt.value, dt.value
+
+
+def hj_rhs(g, V, L_out, stream=None):
+    _check(_lib.hj_rhs(g, _ptr(V), _ptr(L_out), _stream(stream)))
+
+
+def hj_get_schedule(g, t0: float, tf: float, ndim: int, stream=None):
+    alpha = (ctypes.c_double * 4)()
+    dt = ctypes.c_double(0.0)
+    steps = ctypes.c_int64(0)
+    _check(_lib.hj_get_schedule(g, float(t0), float(tf), alpha, ctypes.byref(dt),
+                                ctypes.byref(steps), _stream(stream)))
+    return [alpha[k] for k in range(ndim)], dt.value, steps.value
+
+
+def hj_grid_destroy(g):
+    _check(_lib.hj_grid_destroy(g))
+
+
+class Grid:
+    """Owning wrapper of one hj_grid_t (marshalling only)."""
+
+    def __init__(self, n, lo, hi, periodic=None, prec="fp64"):
+        periodic = periodic or [False] * len(n)
+        mask = sum(1 << d for d, p in enumerate(periodic) if p)
+        self.n = tuple(int(v) for v in n)
+        self.prec = prec
+        self.handle = hj_grid_create(self.n, lo, hi, mask, PREC[prec])
+
+    @classmethod
+    def from_problem(cls, p, prec="fp64") -> "Grid":
+        g = cls(p.n, p.lo, p.hi, p.periodic, prec)
+        g.set_dynamics(p.dynamics, p.params)
+        g.set_scheme(p.scheme, p.order, p.cfl)
+        return g
+
+    def set_dynamics(self, name: str, params):
+        hj_set_dynamics(self.handle, DYN[name], params)
+
+    def set_scheme(self, space="weno5", order=3, cfl=0.8):
+        hj_set_scheme(self.handle, SPACE[space], int(order), cfl)
+
+    def solve(self, V0, V_out, t0, tf, mode="set", stream=None):
+        hj_solve(self.handle, V0, V_out, t0, tf, MODE[mode], stream)
+
+    def step(self, V, V0, t, tf, mode="set", stream=None):
+        return hj_step(self.handle, V, V0, t, tf, MODE[mode], stream)
+
+    def rhs(self, V, L_out, stream=None):
+        hj_rhs(self.handle, V, L_out, stream)
+
+    def schedule(self, t0, tf, stream=None):
+        return hj_get_schedule(self.handle, t0, tf, len(self.n), stream)
+
+    def close(self):
+        if self.handle is not None:
+            hj_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -91,9 +91,10 @@ def sdf_cylinder(n, lo, hi, periodic, radius, axes=(0, 1)) -> np.ndarray:
     grids = np.meshgrid(*xs, indexing="ij", sparse=True)
     r2 = 0.0
     for a in axes:
-        r2 = r2 + grids[a] ** 2
+        if a < len(n):
+            r2 = r2 + grids[a] ** 2
     out = np.sqrt(r2) - radius
-    return np.ascontiguousarray(np.broadcast_to(out, tuple(n)), dtype=np.float64)
+    return np.array(np.broadcast_to(out, tuple(n)), dtype=np.float64, order="C", copy=True)
 
 
 def sdf_box(n, lo, hi, periodic, center, half, axes) -> np.ndarray:
@@ -107,7 +108,7 @@ def sdf_box(n, lo, hi, periodic, center, half, axes) -> np.ndarray:
         outside = outside + np.maximum(qa, 0.0) ** 2
         inside = np.maximum(inside, qa)
     out = np.sqrt(outside) + np.minimum(inside, 0.0)
-    return np.ascontiguousarray(np.broadcast_to(out, tuple(n)), dtype=np.float64)
+    return np.array(np.broadcast_to(out, tuple(n)), dtype=np.float64, order="C", copy=True)
 
 
 def random_field(n, seed=0, amplitude=1.0) -> np.ndarray:
