@@ -24,7 +24,8 @@
  *   R1  D- v_i = (v_i - v_{i-1})/dx, D+ v_i = (v_{i+1} - v_i)/dx; the printed
  *       difference equation has the labels swapped, the upwind rule of Sec. 3.1
  *       (use D- when the speed is positive) fixes the direction.
- *   R2  ENO2: D1_{k+1/2} = (v_{k+1}-v_k)/dx, D2_k = (D1_{k+1/2}-D1_{k-1/2})/(2dx);
+ *   R2  ENO2: D1_{k+1/2} = (v_{k+1}-v_k)/dx, D2_k = (D1_{k+1/2}-D1_{k-1/2})/(2dx)
+ *       (computed with the reciprocals 1/dx and 1/(2dx));
  *       p- = D1_{i-1/2} + dx*m(D2_{i-1}, D2_i), p+ = D1_{i+1/2} - dx*m(D2_i, D2_{i+1}),
  *       m(a,b) = a if |a| <= |b| else b (the <= tie rule printed for ENO3).
  *   R3  WENO5: Jiang-Peng with eps = 1e-6*max(v_k^2) + 1e-99.
@@ -63,6 +64,8 @@ typedef struct {
     long stride[ORC_MAXD];
     long total;
     double lo[ORC_MAXD], hi[ORC_MAXD], dx[ORC_MAXD];
+    double inv_dx[ORC_MAXD];  /* 1/dx */
+    double inv_2dx[ORC_MAXD]; /* 1/(2 dx) */
     int periodic[ORC_MAXD];
     double *x[ORC_MAXD]; /* node coordinates per axis */
     double *cs[ORC_MAXD]; /* cos of the node coordinates */
@@ -91,6 +94,8 @@ static int grid_init(ogrid *g, int nd, const long *n, const double *lo,
         if (n[d] < 2) return -1;
         g->dx[d] = g->periodic[d] ? (hi[d] - lo[d]) / (double)n[d]
                                   : (hi[d] - lo[d]) / (double)(n[d] - 1);
+        g->inv_dx[d] = 1.0 / g->dx[d];
+        g->inv_2dx[d] = 1.0 / (2.0 * g->dx[d]);
         g->total *= n[d];
     }
     /* C order: the last axis is the fastest */
@@ -153,19 +158,27 @@ static double line_value(const ogrid *g, const double *v, long node, int d, long
 /* ------------------------------------------------- one-sided derivatives */
 
 /* Sec. 3.3, Jiang-Peng WENO5 from five consecutive one-sided differences
- * (Osher-Fedkiw eqs. 3.28-3.39); reading R3 for eps. */
+ * (Osher-Fedkiw eqs. 3.28-3.39); reading R3 for eps.  The constant fractions
+ * are multiplied as precomputed doubles and the three weights are normalised
+ * by one division of the weighted sum: the same formulas, written so that a
+ * device implementation can reproduce every rounding. */
+static const double C1_3 = 1.0 / 3.0, C1_6 = 1.0 / 6.0, C5_6 = 5.0 / 6.0,
+                    C7_6 = 7.0 / 6.0, C11_6 = 11.0 / 6.0, C13_12 = 13.0 / 12.0;
+
 static double weno5(double v1, double v2, double v3, double v4, double v5)
 {
-    double phi1 = v1 / 3.0 - 7.0 * v2 / 6.0 + 11.0 * v3 / 6.0;
-    double phi2 = -v2 / 6.0 + 5.0 * v3 / 6.0 + v4 / 3.0;
-    double phi3 = v3 / 3.0 + 5.0 * v4 / 6.0 - v5 / 6.0;
+    /* third-order candidates on the three substencils */
+    double phi1 = v1 * C1_3 - v2 * C7_6 + v3 * C11_6;
+    double phi2 = -v2 * C1_6 + v3 * C5_6 + v4 * C1_3;
+    double phi3 = v3 * C1_3 + v4 * C5_6 - v5 * C1_6;
 
-    double s1 = 13.0 / 12.0 * (v1 - 2.0 * v2 + v3) * (v1 - 2.0 * v2 + v3)
-              + 0.25 * (v1 - 4.0 * v2 + 3.0 * v3) * (v1 - 4.0 * v2 + 3.0 * v3);
-    double s2 = 13.0 / 12.0 * (v2 - 2.0 * v3 + v4) * (v2 - 2.0 * v3 + v4)
-              + 0.25 * (v2 - v4) * (v2 - v4);
-    double s3 = 13.0 / 12.0 * (v3 - 2.0 * v4 + v5) * (v3 - 2.0 * v4 + v5)
-              + 0.25 * (3.0 * v3 - 4.0 * v4 + v5) * (3.0 * v3 - 4.0 * v4 + v5);
+    /* smoothness indicators */
+    double e1 = v1 - 2.0 * v2 + v3, f1 = v1 - 4.0 * v2 + 3.0 * v3;
+    double e2 = v2 - 2.0 * v3 + v4, f2 = v2 - v4;
+    double e3 = v3 - 2.0 * v4 + v5, f3 = 3.0 * v3 - 4.0 * v4 + v5;
+    double s1 = C13_12 * e1 * e1 + 0.25 * f1 * f1;
+    double s2 = C13_12 * e2 * e2 + 0.25 * f2 * f2;
+    double s3 = C13_12 * e3 * e3 + 0.25 * f3 * f3;
 
     double mx = v1 * v1;
     if (v2 * v2 > mx) mx = v2 * v2;
@@ -174,12 +187,12 @@ static double weno5(double v1, double v2, double v3, double v4, double v5)
     if (v5 * v5 > mx) mx = v5 * v5;
     double eps = 1e-6 * mx + 1e-99;
 
+    /* weights alpha_k = gamma_k / (S_k + eps)^2, gamma = (0.1, 0.6, 0.3);
+     * result sum_k alpha_k phi_k / sum_k alpha_k */
     double a1 = 0.1 / ((s1 + eps) * (s1 + eps));
     double a2 = 0.6 / ((s2 + eps) * (s2 + eps));
     double a3 = 0.3 / ((s3 + eps) * (s3 + eps));
-    double sum = a1 + a2 + a3;
-    double w1 = a1 / sum, w2 = a2 / sum, w3 = a3 / sum;
-    return w1 * phi1 + w2 * phi2 + w3 * phi3;
+    return (a1 * phi1 + a2 * phi2 + a3 * phi3) / (a1 + a2 + a3);
 }
 
 /* ENO choice of the smaller second difference, tie to the first argument
@@ -197,12 +210,13 @@ static void derivs_at(const ogrid *g, const double *v, long node, int d,
 {
     long i = axis_index(g, node, d);
     double dx = g->dx[d];
+    double inv_dx = g->inv_dx[d];
     if (scheme == ORC_UPWIND1) {
         double vm = line_value(g, v, node, d, i - 1);
         double vc = line_value(g, v, node, d, i);
         double vp = line_value(g, v, node, d, i + 1);
-        *pm = (vc - vm) / dx;
-        *pp = (vp - vc) / dx;
+        *pm = (vc - vm) * inv_dx;
+        *pp = (vp - vc) * inv_dx;
         return;
     }
     if (scheme == ORC_ENO2) {
@@ -211,10 +225,10 @@ static void derivs_at(const ogrid *g, const double *v, long node, int d,
         for (int k = 0; k < 5; ++k) s[k] = line_value(g, v, node, d, i - 2 + k);
         /* first divided differences at half points i-3/2 .. i+3/2 */
         double d1[4];
-        for (int k = 0; k < 4; ++k) d1[k] = (s[k + 1] - s[k]) / dx;
+        for (int k = 0; k < 4; ++k) d1[k] = (s[k + 1] - s[k]) * inv_dx;
         /* second divided differences at nodes i-1, i, i+1 */
         double d2[3];
-        for (int k = 0; k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) / (2.0 * dx);
+        for (int k = 0; k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) * g->inv_2dx[d];
         *pm = d1[1] + dx * eno_pick(d2[0], d2[1]);
         *pp = d1[2] - dx * eno_pick(d2[1], d2[2]);
         return;
@@ -223,7 +237,7 @@ static void derivs_at(const ogrid *g, const double *v, long node, int d,
     double s[7];
     for (int k = 0; k < 7; ++k) s[k] = line_value(g, v, node, d, i - 3 + k);
     double d1[6];
-    for (int k = 0; k < 6; ++k) d1[k] = (s[k + 1] - s[k]) / dx;
+    for (int k = 0; k < 6; ++k) d1[k] = (s[k + 1] - s[k]) * inv_dx;
     /* p-: D-v at i-2..i+2 = D1 at i-5/2..i+3/2 */
     *pm = weno5(d1[0], d1[1], d1[2], d1[3], d1[4]);
     /* p+: D+v at i+2..i-2 = D1 at i+5/2..i-3/2 */

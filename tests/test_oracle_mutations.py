@@ -15,14 +15,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "hj_oracle.c")
 
 MUTATIONS = {
-    "upwind_directions_swapped": ("*pm = (vc - vm) / dx;\n        *pp = (vp - vc) / dx;",
-                                  "*pm = (vp - vc) / dx;\n        *pp = (vc - vm) / dx;"),
+    "upwind_directions_swapped": ("*pm = (vc - vm) * inv_dx;\n        *pp = (vp - vc) * inv_dx;",
+                                  "*pm = (vp - vc) * inv_dx;\n        *pp = (vc - vm) * inv_dx;"),
     "eno2_right_correction_sign": ("*pp = d1[2] - dx * eno_pick", "*pp = d1[2] + dx * eno_pick"),
     "eno2_picks_larger": ("return fabs(a) <= fabs(b) ? a : b;", "return fabs(a) <= fabs(b) ? b : a;"),
-    "eno2_second_difference_scale": ("(d1[k + 1] - d1[k]) / (2.0 * dx)", "(d1[k + 1] - d1[k]) / dx"),
+    "eno2_second_difference_scale": ("(d1[k + 1] - d1[k]) * g->inv_2dx[d]",
+                                     "(d1[k + 1] - d1[k]) * inv_dx"),
     "weno_linear_weights_swapped": ("double a1 = 0.1 /", "double a1 = 0.3 /"),
-    "weno_candidate_coefficient": ("11.0 * v3 / 6.0", "10.0 * v3 / 6.0"),
-    "weno_smoothness_term": ("0.25 * (v2 - v4) * (v2 - v4)", "0.25 * (v2 + v4) * (v2 - v4)"),
+    "weno_candidate_coefficient": ("v3 * C11_6", "v3 * C5_6"),
+    "weno_smoothness_term": ("f2 = v2 - v4;", "f2 = v2 + v4;"),
     "weno_right_stencil_order": ("weno5(d1[5], d1[4], d1[3], d1[2], d1[1])",
                                  "weno5(d1[1], d1[2], d1[3], d1[4], d1[5])"),
     "lf_dissipation_sign": ("hhat -= alpha[d] *", "hhat += alpha[d] *"),
