@@ -31,6 +31,34 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (KiB per dispatch, scaled by a 512 MiB copy: x2.000 and
+# x1.000), keyed by precision, with the hash of the kernel sources they were
+# taken on; a changed source reports null until the counters are re-taken.
+MEASURED_TRAFFIC = {
+    "fp64": {"src_hash": "3585621594a2fdbd", "fetch_kib": 17593.6, "write_kib": 8049.2,
+             "fetch_scale": 2.0, "write_scale": 1.0},
+}
+
+
+def source_hash() -> str:
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2507_11542_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec: str):
+    m = MEASURED_TRAFFIC.get(prec)
+    if not m or m["src_hash"] != source_hash():
+        return None
+    return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
+
 
 def weno5_flops_per_node_stage(ndim: int) -> float:
     """Algorithmic floating-point operations of one stage at one node, counted
@@ -82,6 +110,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=40,
                     help="RK steps timed with HIP events for the kernel roofline")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (calibrates "
+                         "the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only; multi-GPU runs are not part of this build "
@@ -143,6 +174,14 @@ def main() -> int:
         err = float(np.abs(got - data[:, 1]).max())
     g.close()
 
+    if args.copy_mib:
+        src = torch.empty(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
     rec = {
         "metric": METRIC,
         "value": value,
@@ -160,7 +199,8 @@ def main() -> int:
                    "grid": list(p.n), "rk_steps": nsteps, "dt": dt, "alpha": alpha,
                    "path": "plain (hj_solve, one solve at a time)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(args.prec),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "stage_kernel<%s,3,WENO5,REL_DUBINS>" % args.prec,
                      "launch_us": launch_s * 1e6,
                      "algorithmic_hbm_GBs": hbm_gbs,

@@ -183,6 +183,7 @@ StageArgs<T> base_args(hj_grid_t g)
         a.tab_off[d] = g->tab_off[d];
         a.dx[d] = T(g->dx[d]);
         a.inv_dx[d] = T(1.0 / g->dx[d]);
+        a.inv_2dx[d] = T(1.0 / (2.0 * g->dx[d]));
         a.alpha[d] = T(g->alpha[d]);
     }
     a.total = uint32_t(g->total);

@@ -32,7 +32,8 @@ struct StageArgs {
     uint32_t total;
     uint32_t periodic;  // bit d: axis d periodic
     T dx[kMaxDim];
-    T inv_dx[kMaxDim];
+    T inv_dx[kMaxDim];   // 1/dx (FP64 on the host, then rounded to T)
+    T inv_2dx[kMaxDim];  // 1/(2 dx)
     T alpha[kMaxDim];
     T prm[8];
     T dt, wb, w2, den;

@@ -15,20 +15,6 @@
 
 namespace hj {
 
-template <typename T>
-struct Num;
-template <>
-struct Num<double> {
-    static constexpr double eps_floor = 1e-99;
-    __device__ static inline double recip(double x) { return 1.0 / x; }
-};
-template <>
-struct Num<float> {
-    // 1e-99 underflows in float; the floor keeps (S + eps)^2 a normal float.
-    static constexpr float eps_floor = 1e-18f;
-    __device__ static inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-};
-
 template <int SCH>
 struct Halo;
 template <>
@@ -40,15 +26,24 @@ struct Halo<kWeno5> { static constexpr int w = 3; };
 
 // Jiang-Peng WENO5 approximation from five consecutive one-sided differences
 // (Sec. 3.3; Osher-Fedkiw eqs. 3.28-3.39), eps = 1e-6 max v_k^2 + floor.
+//
+// FP64: candidates, smoothness indicators and weights in the written order
+// with correctly rounded divisions, built without contraction, so every
+// rounding equals that of a plain FP64 evaluation of the same formulas.  The
+// discrete scheme amplifies rounding differences by up to ~1e11 over a long
+// horizon near the ridges of a game's value function, so FP64 results are only
+// comparable at 1e-12 when the rounding is reproduced.
+// FP32: fused multiply-adds and hardware reciprocals (v_rcp_f32); the floor
+// is 1e-18 because 1e-99 underflows in float.
 template <typename T>
 __device__ inline T weno5(T v1, T v2, T v3, T v4, T v5)
 {
-    constexpr T c13_12 = T(13) / T(12);
-    constexpr T c1_3 = T(1) / T(3);
-    constexpr T c1_6 = T(1) / T(6);
-    constexpr T c5_6 = T(5) / T(6);
-    constexpr T c7_6 = T(7) / T(6);
-    constexpr T c11_6 = T(11) / T(6);
+    constexpr T c13_12 = T(13.0 / 12.0);
+    constexpr T c1_3 = T(1.0 / 3.0);
+    constexpr T c1_6 = T(1.0 / 6.0);
+    constexpr T c5_6 = T(5.0 / 6.0);
+    constexpr T c7_6 = T(7.0 / 6.0);
+    constexpr T c11_6 = T(11.0 / 6.0);
 
     const T phi1 = v1 * c1_3 - v2 * c7_6 + v3 * c11_6;
     const T phi2 = -v2 * c1_6 + v3 * c5_6 + v4 * c1_3;
@@ -66,15 +61,19 @@ __device__ inline T weno5(T v1, T v2, T v3, T v4, T v5)
     mx = fmax(mx, v3 * v3);
     mx = fmax(mx, v4 * v4);
     mx = fmax(mx, v5 * v5);
-    const T eps = T(1e-6) * mx + Num<T>::eps_floor;
-
-    const T q1 = (s1 + eps) * (s1 + eps);
-    const T q2 = (s2 + eps) * (s2 + eps);
-    const T q3 = (s3 + eps) * (s3 + eps);
-    const T a1 = T(0.1) * Num<T>::recip(q1);
-    const T a2 = T(0.6) * Num<T>::recip(q2);
-    const T a3 = T(0.3) * Num<T>::recip(q3);
-    return (a1 * phi1 + a2 * phi2 + a3 * phi3) * Num<T>::recip(a1 + a2 + a3);
+    if constexpr (sizeof(T) == 8) {
+        const T eps = T(1e-6) * mx + T(1e-99);
+        const T a1 = T(0.1) / ((s1 + eps) * (s1 + eps));
+        const T a2 = T(0.6) / ((s2 + eps) * (s2 + eps));
+        const T a3 = T(0.3) / ((s3 + eps) * (s3 + eps));
+        return (a1 * phi1 + a2 * phi2 + a3 * phi3) / (a1 + a2 + a3);
+    } else {
+        const T eps = T(1e-6) * mx + T(1e-18);
+        const T a1 = T(0.1) * __builtin_amdgcn_rcpf((s1 + eps) * (s1 + eps));
+        const T a2 = T(0.6) * __builtin_amdgcn_rcpf((s2 + eps) * (s2 + eps));
+        const T a3 = T(0.3) * __builtin_amdgcn_rcpf((s3 + eps) * (s3 + eps));
+        return (a1 * phi1 + a2 * phi2 + a3 * phi3) * __builtin_amdgcn_rcpf(a1 + a2 + a3);
+    }
 }
 
 // ENO2 choice of the smaller second difference; ties go to the first (<=).
@@ -106,10 +105,12 @@ __device__ inline T line_value(const T *__restrict__ v, uint32_t node, int i, in
 }
 
 // p- and p+ along one axis at one node (Sec. 3.1-3.3).
+// First divided differences use the reciprocal cell size 1/dx, second ones
+// 1/(2 dx) (both computed once on the host in FP64).
 template <typename T, int SCH>
 __device__ inline void axis_derivs(const T *__restrict__ v, uint32_t node, int i, int n,
-                                   uint32_t stride, bool periodic, T dx, T inv_dx, T &pm,
-                                   T &pp, T &center)
+                                   uint32_t stride, bool periodic, T dx, T inv_dx, T inv_2dx,
+                                   T &pm, T &pp, T &center)
 {
     constexpr int W = Halo<SCH>::w;
     T s[2 * W + 1];
@@ -124,17 +125,15 @@ __device__ inline void axis_derivs(const T *__restrict__ v, uint32_t node, int i
     }
     center = s[W];
     if constexpr (SCH == kUpwind1) {
-        pm = (s[1] - s[0]) / dx;
-        pp = (s[2] - s[1]) / dx;
+        pm = (s[1] - s[0]) * inv_dx;
+        pp = (s[2] - s[1]) * inv_dx;
     } else if constexpr (SCH == kEno2) {
-        // divided-difference table as in Sec. 3.2 (exact divisions, so the
-        // ENO choice is taken on the same values as a plain reference)
+        // divided-difference table of Sec. 3.2
         T d1[4], d2[3];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) d1[k] = (s[k + 1] - s[k]) / dx;
-        const T two_dx = T(2) * dx;
+        for (int k = 0; k < 4; ++k) d1[k] = (s[k + 1] - s[k]) * inv_dx;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) / two_dx;
+        for (int k = 0; k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) * inv_2dx;
         pm = d1[1] + dx * eno_pick(d2[0], d2[1]);
         pp = d1[2] - dx * eno_pick(d2[1], d2[2]);
     } else {
@@ -180,11 +179,11 @@ __device__ inline T hamiltonian(const StageArgs<T> &a, const int *ii, const T *p
     }
 }
 
+// One node of one stage: derivatives along every axis, Lax-Friedrichs
+// right-hand side, RK combination and tube minimum; writes a.out[node].
 template <typename T, int D, int SCH, int DYN>
-__global__ __launch_bounds__(256) void stage_kernel(const StageArgs<T> a)
+__device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
 {
-    const uint32_t node = blockIdx.x * 256u + threadIdx.x;
-    if (node >= a.total) return;
     int ii[D];
     {
         uint32_t r = node;
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(256) void stage_kernel(const StageArgs<T> a)
 #pragma unroll
     for (int d = 0; d < D; ++d)
         axis_derivs<T, SCH>(a.vs, node, ii[d], int(a.n[d]), a.stride[d], (a.periodic >> d) & 1u,
-                            a.dx[d], a.inv_dx[d], pm[d], pp[d], center);
+                            a.dx[d], a.inv_dx[d], a.inv_2dx[d], pm[d], pp[d], center);
     T pbar[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) pbar[d] = (pp[d] + pm[d]) * T(0.5);
@@ -219,6 +218,14 @@ __global__ __launch_bounds__(256) void stage_kernel(const StageArgs<T> a)
     }
     if (a.tube) val = fmin(val, a.v0[node]);
     a.out[node] = val;
+}
+
+template <typename T, int D, int SCH, int DYN>
+__global__ __launch_bounds__(256) void stage_kernel(const StageArgs<T> a)
+{
+    const uint32_t node = blockIdx.x * 256u + threadIdx.x;
+    if (node >= a.total) return;
+    stage_node<T, D, SCH, DYN>(a, node);
 }
 
 template <typename T, int D, int SCH, int DYN>

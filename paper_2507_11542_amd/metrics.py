@@ -74,7 +74,8 @@ def region_errors(v: np.ndarray, ref: np.ndarray, dx: Sequence[float],
                   periodic: Sequence[bool], band_cells: float = 3.0,
                   edge_cells: int = 6) -> Dict[str, float]:
     """Max-abs error overall, in the front band |ref| < band_cells*max(dx),
-    within edge_cells of a bounded edge, and in the rest (interior)."""
+    in that band away from the bounded edges (band_inner), within edge_cells
+    of a bounded edge, and in the rest (interior)."""
     v = np.asarray(v, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     err = np.abs(v - ref)
@@ -94,4 +95,4 @@ def region_errors(v: np.ndarray, ref: np.ndarray, dx: Sequence[float],
         return float(err[mask].max()) if np.any(mask) else 0.0
 
     return {"max_abs": float(err.max()) if err.size else 0.0, "band": mx(band),
-            "edge": mx(edge), "interior": mx(interior)}
+            "band_inner": mx(band & ~edge), "edge": mx(edge), "interior": mx(interior)}
