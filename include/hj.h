@@ -126,6 +126,48 @@ hj_status hj_rhs(hj_grid_t g, const void *V, void *L_out, void *hip_stream);
 hj_status hj_get_schedule(hj_grid_t g, double t0, double tf, double *alpha, double *dt,
                           int64_t *n_steps, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batched solves.  n independent grids that share ndim, dynamics kind,
+ * derivative scheme (ENO2 or WENO5), RK order (2 or 3), precision and device
+ * advance together: one fused launch per RK-stage round covers the tiles of
+ * every instance still running, so instances of any size and step count run
+ * side by side, and each keeps its own alpha, dt and FP64 time t on the device
+ * (Sec. 5 time loop per instance).  The round launches are captured once in a
+ * hipGraph and replayed; the instance tables live in device memory and are
+ * uploaded before each replay.  Results equal the instances' hj_solve results
+ * bit for bit (same per-node arithmetic, same FP64 step sizes). */
+typedef struct hj_batch_s *hj_batch_t;
+
+/* New batch engine on the current device. */
+hj_status hj_batch_create(hj_batch_t *out);
+
+/* Launch shape: tile_nodes nodes per tile (multiple of 256, in [256, 2^22];
+ * default 4096), workgroups of 256 threads per round launch striding over the
+ * round's tiles (in [1, 65536]; default 1024), use_graph != 0 to replay a
+ * captured hipGraph (default) instead of direct launches. */
+hj_status hj_batch_config(hj_batch_t b, int tile_nodes, int workgroups, int use_graph);
+
+/* Solve instance i from V0s[i] over [t0[i], tf[i]] in modes[i] into Vouts[i]
+ * (device arrays of grid i's size and precision; V_out must not overlap any
+ * V0 or other V_out).  The grids' dynamics and schemes must be set.  Runs one
+ * alpha reduction per instance (one synchronisation for all), then enqueues
+ * the uploads and the launch on hip_stream and returns.  A second call waits
+ * for the previous one of the same handle to finish before it reuses the
+ * tables.  HJ_E_ARG on mismatched or invalid instances, HJ_E_UNSUPPORTED for
+ * first-order schemes or RK1. */
+hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
+                         void *const *Vouts, const double *t0, const double *tf,
+                         const hj_mode *modes, void *hip_stream);
+
+/* Waits for the last hj_solve_batch on hip_stream.  t_final (n doubles, may
+ * be NULL) receives each instance's device-accumulated final time, items
+ * (may be NULL) the number of tiles over all rounds.  The grids passed to
+ * hj_solve_batch must stay alive until this returns. */
+hj_status hj_batch_wait(hj_batch_t b, void *hip_stream, double *t_final, int64_t *items);
+
+/* Frees the engine (waits for its last batch).  NULL is accepted. */
+hj_status hj_batch_destroy(hj_batch_t b);
+
 /* Frees the handle, its tables and stage buffers (after the device is idle
  * for this handle's work).  NULL is accepted. */
 hj_status hj_grid_destroy(hj_grid_t g);

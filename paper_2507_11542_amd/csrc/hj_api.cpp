@@ -17,14 +17,27 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hj.h"
-#include "hj_internal.h"
+#include "hj_host.h"
 
 using namespace hj;
 
 namespace {
 
 thread_local std::string g_err;
+
+int halo_of(int space) { return space == HJ_UPWIND1 ? 1 : (space == HJ_ENO2 ? 2 : 3); }
+
+// Testing hook: HJ_FAULT_OOM=1 makes every device allocation of the library
+// report HJ_E_OOM without calling the allocator.
+bool fault_oom()
+{
+    const char *s = std::getenv("HJ_FAULT_OOM");
+    return s && s[0] == '1';
+}
+
+}  // namespace
+
+namespace hj {
 
 hj_status fail(hj_status s, const std::string &msg)
 {
@@ -38,64 +51,12 @@ hj_status hip_fail(hipError_t e, const char *what)
     return e == hipErrorOutOfMemory ? HJ_E_OOM : HJ_E_DEVICE;
 }
 
-#define HJ_HIP(call, what)                                   \
-    do {                                                     \
-        hipError_t e_ = (call);                              \
-        if (e_ != hipSuccess) return hip_fail(e_, (what));   \
-    } while (0)
-
-int halo_of(int space) { return space == HJ_UPWIND1 ? 1 : (space == HJ_ENO2 ? 2 : 3); }
-
-// Testing hook: HJ_FAULT_OOM=1 makes every device allocation of the library
-// report HJ_E_OOM without calling the allocator.
-bool fault_oom()
-{
-    const char *s = std::getenv("HJ_FAULT_OOM");
-    return s && s[0] == '1';
-}
-
 hj_status dev_alloc(void **p, size_t bytes, const char *what)
 {
     if (fault_oom()) return fail(HJ_E_OOM, std::string(what) + ": injected allocation failure");
     HJ_HIP(hipMalloc(p, bytes), what);
     return HJ_OK;
 }
-
-}  // namespace
-
-struct hj_grid_s {
-    int nd = 0;
-    int64_t n[kMaxDim] = {1, 1, 1, 1};
-    double lo[kMaxDim] = {0, 0, 0, 0}, hi[kMaxDim] = {0, 0, 0, 0}, dx[kMaxDim] = {1, 1, 1, 1};
-    uint32_t pmask = 0;
-    hj_precision prec = HJ_FP64;
-    int64_t total = 0;
-    uint32_t stride[kMaxDim] = {0, 0, 0, 0};
-    uint32_t tab_off[kMaxDim] = {0, 0, 0, 0};
-    int device = 0;
-
-    int dyn = -1;
-    double prm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-
-    int space = HJ_WENO5;
-    int order = 3;
-    double cfl = 0.8;
-
-    double *tab64 = nullptr;   // device, FP64 tables (alpha and FP64 stages)
-    float *tab32 = nullptr;    // device, FP32 tables (FP32 stages)
-    void *bufA = nullptr;      // stage buffers
-    void *bufB = nullptr;
-    double *partial = nullptr; // alpha pass-1 partial maxima
-    double *alpha_dev = nullptr;
-    double *alpha_host = nullptr;  // pinned
-    bool alpha_valid = false;
-    double alpha[kMaxDim] = {0, 0, 0, 0};
-
-    size_t elem() const { return prec == HJ_FP64 ? sizeof(double) : sizeof(float); }
-    size_t bytes() const { return size_t(total) * elem(); }
-};
-
-namespace {
 
 hj_status use_device(hj_grid_t g)
 {
@@ -126,8 +87,8 @@ hj_status check_ready(hj_grid_t g)
 }
 
 // GPU max-reduction of the speed bounds (Sec. 4), read back through pinned
-// memory: the one synchronisation of a solve.
-hj_status compute_alpha(hj_grid_t g, hipStream_t s)
+// memory.
+hj_status launch_alpha_readback(hj_grid_t g, hipStream_t s)
 {
     AlphaArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -143,9 +104,22 @@ hj_status compute_alpha(hj_grid_t g, hipStream_t s)
     HJ_HIP(hipMemcpyAsync(g->alpha_host, g->alpha_dev, sizeof(double) * g->nd,
                           hipMemcpyDeviceToHost, s),
            "alpha read-back");
-    HJ_HIP(hipStreamSynchronize(s), "alpha synchronise");
+    return HJ_OK;
+}
+
+void accept_alpha(hj_grid_t g)
+{
     for (int d = 0; d < g->nd; ++d) g->alpha[d] = g->alpha_host[d];
     g->alpha_valid = true;
+}
+
+// The one synchronisation of a solve.
+hj_status compute_alpha(hj_grid_t g, hipStream_t s)
+{
+    hj_status st = launch_alpha_readback(g, s);
+    if (st != HJ_OK) return st;
+    HJ_HIP(hipStreamSynchronize(s), "alpha synchronise");
+    accept_alpha(g);
     return HJ_OK;
 }
 
@@ -157,7 +131,7 @@ double cfl_dt(hj_grid_t g)
     return rate > 0.0 ? g->cfl / rate : INFINITY;
 }
 
-constexpr double kEpsT = 100.0 * 2.220446049250313e-16;
+const double kEpsT = 100.0 * 2.220446049250313e-16;
 
 // Sec. 5 time loop: step sizes min(dt, tf - t) until tf - t < eps (tf - t0).
 void schedule(double dt, double t0, double tf, std::vector<double> *hs)
@@ -191,6 +165,12 @@ StageArgs<T> base_args(hj_grid_t g)
     for (int k = 0; k < 8; ++k) a.prm[k] = T(g->prm[k]);
     return a;
 }
+template StageArgs<double> base_args<double>(hj_grid_t g);
+template StageArgs<float> base_args<float>(hj_grid_t g);
+
+}  // namespace hj
+
+namespace {
 
 template <typename T>
 hj_status launch(hj_grid_t g, const StageArgs<T> &a, hipStream_t s);

@@ -1,0 +1,426 @@
+// Batched solves (C ABI part of include/hj.h): many independent grids that
+// share ndim, dynamics kind, derivative scheme, RK order and precision are
+// advanced together, one fused launch per RK-stage round over every running
+// instance (hj_batch_impl.h).  The sequence of round launches is captured once
+// in a hipGraph and replayed; every table the kernels read lives in device
+// memory, so a new batch composition only needs uploads before the replay
+// (and a new capture only when it needs more rounds than were captured).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "hj_batch_impl.h"
+#include "hj_host.h"
+
+using namespace hj;
+
+namespace hj {
+hipError_t batch_launch_f64(int ndim, int space, int dyn, const BatchPtrs<double> &p,
+                            uint32_t rounds, uint32_t workgroups, hipStream_t s);
+hipError_t batch_launch_f32(int ndim, int space, int dyn, const BatchPtrs<float> &p,
+                            uint32_t rounds, uint32_t workgroups, hipStream_t s);
+}  // namespace hj
+
+struct hj_batch_s {
+    int device = 0;
+    uint32_t tile_nodes = 4096;
+    uint32_t workgroups = 1024;
+    bool use_graph = true;
+
+    // device tables and their capacities
+    uint32_t cap_inst = 0, cap_rounds = 0;
+    void *inst = nullptr;        // BatchInst<T>[cap_inst]
+    BatchCtl *ctl = nullptr;     // [cap_inst]
+    uint32_t *sorted = nullptr;  // [cap_inst]
+    uint32_t *tile_pre = nullptr;   // [cap_inst + 1]
+    uint32_t *round_off = nullptr;  // [cap_rounds + 1]
+    BatchGlobal *gl = nullptr;
+    // pinned host staging
+    void *h_inst = nullptr;
+    uint32_t *h_sorted = nullptr, *h_tile_pre = nullptr, *h_round_off = nullptr;
+    BatchGlobal *h_gl = nullptr;
+    BatchCtl *h_ctl_out = nullptr;    // read back after a solve
+    uint32_t last_n = 0;
+    std::vector<uint32_t> last_steps;
+    // recorded after the read-back of a solve: the next solve reuses the
+    // tables and staging buffers only after it
+    hipEvent_t done_evt = nullptr;
+    bool pending = false;
+
+    // captured graph and the launch it was captured for
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int key_nd = -1, key_space = -1, key_dyn = -1, key_prec = -1;
+    uint32_t key_wg = 0, key_rounds = 0;
+};
+
+namespace {
+
+size_t inst_size(hj_precision p)
+{
+    return p == HJ_FP64 ? sizeof(BatchInst<double>) : sizeof(BatchInst<float>);
+}
+
+void free_tables(hj_batch_t b)
+{
+    if (b->inst) (void)hipFree(b->inst);
+    if (b->ctl) (void)hipFree(b->ctl);
+    if (b->sorted) (void)hipFree(b->sorted);
+    if (b->tile_pre) (void)hipFree(b->tile_pre);
+    if (b->round_off) (void)hipFree(b->round_off);
+    if (b->h_inst) (void)hipHostFree(b->h_inst);
+    if (b->h_sorted) (void)hipHostFree(b->h_sorted);
+    if (b->h_tile_pre) (void)hipHostFree(b->h_tile_pre);
+    if (b->h_round_off) (void)hipHostFree(b->h_round_off);
+    if (b->h_ctl_out) (void)hipHostFree(b->h_ctl_out);
+    b->inst = b->ctl = nullptr;
+    b->sorted = b->tile_pre = b->round_off = nullptr;
+    b->h_inst = nullptr;
+    b->h_sorted = b->h_tile_pre = b->h_round_off = nullptr;
+    b->h_ctl_out = nullptr;
+    b->cap_inst = b->cap_rounds = 0;
+}
+
+void drop_graph(hj_batch_t b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->key_nd = -1;
+}
+
+hj_status host_alloc(void **p, size_t bytes, const char *what)
+{
+    HJ_HIP(hipHostMalloc(p, bytes, 0), what);
+    return HJ_OK;
+}
+
+// Grow the tables to hold n instances and `rounds` rounds.  Any change of a
+// device address invalidates the captured graph.
+hj_status reserve(hj_batch_t b, uint32_t n, uint32_t rounds)
+{
+    if (n <= b->cap_inst && rounds <= b->cap_rounds) return HJ_OK;
+    const uint32_t ci = std::max(n, b->cap_inst), cr = std::max(rounds, b->cap_rounds);
+    drop_graph(b);
+    free_tables(b);
+    hj_status s;
+    const size_t isz = std::max(sizeof(BatchInst<double>), sizeof(BatchInst<float>));
+    if ((s = dev_alloc(&b->inst, isz * ci, "batch instance table")) != HJ_OK) return s;
+    if ((s = dev_alloc((void **)&b->ctl, sizeof(BatchCtl) * ci, "batch control")) != HJ_OK)
+        return s;
+    if ((s = dev_alloc((void **)&b->sorted, sizeof(uint32_t) * ci, "batch order")) != HJ_OK)
+        return s;
+    if ((s = dev_alloc((void **)&b->tile_pre, sizeof(uint32_t) * (ci + 1), "batch tiles")) !=
+        HJ_OK)
+        return s;
+    if ((s = dev_alloc((void **)&b->round_off, sizeof(uint32_t) * (cr + 1), "batch rounds")) !=
+        HJ_OK)
+        return s;
+    if ((s = host_alloc(&b->h_inst, isz * ci, "pinned instance table")) != HJ_OK) return s;
+    if ((s = host_alloc((void **)&b->h_sorted, sizeof(uint32_t) * ci, "pinned order")) != HJ_OK)
+        return s;
+    if ((s = host_alloc((void **)&b->h_tile_pre, sizeof(uint32_t) * (ci + 1), "pinned tiles")) !=
+        HJ_OK)
+        return s;
+    if ((s = host_alloc((void **)&b->h_round_off, sizeof(uint32_t) * (cr + 1),
+                        "pinned rounds")) != HJ_OK)
+        return s;
+    if ((s = host_alloc((void **)&b->h_ctl_out, sizeof(BatchCtl) * ci, "pinned control")) !=
+        HJ_OK)
+        return s;
+    b->cap_inst = ci;
+    b->cap_rounds = cr;
+    return HJ_OK;
+}
+
+template <typename T>
+BatchPtrs<T> ptrs(hj_batch_t b)
+{
+    BatchPtrs<T> p;
+    p.inst = (const BatchInst<T> *)b->inst;
+    p.ctl = b->ctl;
+    p.sorted = b->sorted;
+    p.tile_pre = b->tile_pre;
+    p.round_off = b->round_off;
+    p.gl = b->gl;
+    return p;
+}
+
+hipError_t launch_any(hj_batch_t b, int nd, int space, int dyn, hj_precision prec,
+                      uint32_t rounds, hipStream_t s)
+{
+    if (prec == HJ_FP64)
+        return batch_launch_f64(nd, space, dyn, ptrs<double>(b), rounds, b->workgroups, s);
+    return batch_launch_f32(nd, space, dyn, ptrs<float>(b), rounds, b->workgroups, s);
+}
+
+// The init kernel and the round launches, captured once per kernel variant,
+// launch width and round capacity; replays read the current tables and skip
+// the captured rounds beyond the batch's own.
+hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, uint32_t rounds,
+              hipStream_t s)
+{
+    if (!b->use_graph) {
+        hipError_t e = launch_any(b, nd, space, dyn, prec, rounds, s);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+        return HJ_OK;
+    }
+    if (!(b->exec && b->key_nd == nd && b->key_space == space && b->key_dyn == dyn &&
+          b->key_prec == prec && b->key_wg == b->workgroups && rounds <= b->key_rounds)) {
+        drop_graph(b);
+        const uint32_t cap = (rounds + 63u) & ~63u;
+        if (!b->capture_stream)
+            HJ_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking),
+                   "capture stream");
+        hipGraph_t graph = nullptr;
+        HJ_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal),
+               "begin capture");
+        hipError_t e = launch_any(b, nd, space, dyn, prec, cap, b->capture_stream);
+        hipError_t e2 = hipStreamEndCapture(b->capture_stream, &graph);
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e, "batch launch (capture)");
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return hip_fail(e, "graph instantiate");
+        }
+        b->key_nd = nd;
+        b->key_space = space;
+        b->key_dyn = dyn;
+        b->key_prec = prec;
+        b->key_wg = b->workgroups;
+        b->key_rounds = cap;
+    }
+    HJ_HIP(hipGraphLaunch(b->exec, s), "graph launch");
+    return HJ_OK;
+}
+
+template <typename T>
+void fill_inst(void *dst, hj_grid_t g, void *vout, const void *v0, double dt, double t0,
+               double tf, uint32_t tiles, uint32_t steps, bool tube)
+{
+    BatchInst<T> in;
+    std::memset(&in, 0, sizeof(in));
+    in.geo = base_args<T>(g);
+    in.v = (T *)vout;
+    in.a = (T *)g->bufA;
+    in.b = (T *)g->bufB;
+    in.v0 = (const T *)v0;
+    in.dt = dt;
+    in.t0 = t0;
+    in.tf = tf;
+    in.tiles = tiles;
+    in.steps = steps;
+    in.tube = tube ? 1 : 0;
+    std::memcpy(dst, &in, sizeof(in));
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = uintptr_t(a), y = uintptr_t(b);
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+hj_status hj_batch_create(hj_batch_t *out)
+{
+    if (!out) return fail(HJ_E_ARG, "out is NULL");
+    *out = nullptr;
+    hj_batch_s *b = new (std::nothrow) hj_batch_s();
+    if (!b) return fail(HJ_E_OOM, "host allocation of the batch handle");
+    hj_status s = HJ_OK;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) s = hip_fail(e, "hipGetDevice");
+    if (s == HJ_OK) s = dev_alloc((void **)&b->gl, sizeof(BatchGlobal), "batch globals");
+    if (s == HJ_OK) s = host_alloc((void **)&b->h_gl, sizeof(BatchGlobal), "pinned globals");
+    if (s == HJ_OK) {
+        e = hipEventCreateWithFlags(&b->done_evt, hipEventDisableTiming);
+        if (e != hipSuccess) s = hip_fail(e, "batch event");
+    }
+    if (s != HJ_OK) {
+        hj_batch_destroy(b);
+        return s;
+    }
+    *out = b;
+    return HJ_OK;
+}
+
+hj_status hj_batch_config(hj_batch_t b, int tile_nodes, int workgroups, int use_graph)
+{
+    if (!b) return fail(HJ_E_ARG, "null batch handle");
+    if (tile_nodes < 256 || tile_nodes > (1 << 22) || (tile_nodes & 255))
+        return fail(HJ_E_ARG, "tile_nodes must be a multiple of 256 in [256, 2^22]");
+    if (workgroups < 1 || workgroups > 65536) return fail(HJ_E_ARG, "workgroups in [1, 65536]");
+    if (b->workgroups != uint32_t(workgroups)) drop_graph(b);
+    b->tile_nodes = uint32_t(tile_nodes);
+    b->workgroups = uint32_t(workgroups);
+    b->use_graph = use_graph != 0;
+    return HJ_OK;
+}
+
+hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
+                         void *const *Vouts, const double *t0, const double *tf,
+                         const hj_mode *modes, void *hip_stream)
+{
+    if (!b) return fail(HJ_E_ARG, "null batch handle");
+    if (n < 1 || !gs || !V0s || !Vouts || !t0 || !tf || !modes)
+        return fail(HJ_E_ARG, "need n >= 1 and non-NULL arrays");
+    hj_status s;
+    const hj_grid_t g0 = gs[0];
+    for (int i = 0; i < n; ++i) {
+        const hj_grid_t g = gs[i];
+        if ((s = check_ready(g)) != HJ_OK) return s;
+        if (g->nd != g0->nd || g->dyn != g0->dyn || g->space != g0->space ||
+            g->order != g0->order || g->prec != g0->prec || g->device != b->device)
+            return fail(HJ_E_ARG, "instances must share ndim, dynamics, scheme, RK order, "
+                                  "precision and device");
+        if (!V0s[i] || !Vouts[i]) return fail(HJ_E_ARG, "NULL V0 or V_out");
+        if (modes[i] != HJ_SET && modes[i] != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
+        if (!(std::isfinite(t0[i]) && std::isfinite(tf[i]) && tf[i] >= t0[i]))
+            return fail(HJ_E_ARG, "need finite t0 <= tf");
+        if (overlap(V0s[i], g->bytes(), Vouts[i], g->bytes()))
+            return fail(HJ_E_ARG, "V_out overlaps V0 for instance " + std::to_string(i));
+        for (int j = 0; j < i; ++j)
+            if (overlap(Vouts[i], g->bytes(), Vouts[j], gs[j]->bytes()) ||
+                overlap(Vouts[i], g->bytes(), V0s[j], gs[j]->bytes()))
+                return fail(HJ_E_ARG, "instances " + std::to_string(j) + " and " +
+                                          std::to_string(i) + " share memory");
+    }
+    if (g0->space == HJ_UPWIND1 || g0->order == 1)
+        return fail(HJ_E_UNSUPPORTED, "batched solves support ENO2/WENO5 with RK2/RK3");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HJ_HIP(hipSetDevice(b->device), "hipSetDevice");
+    if (b->pending) {
+        HJ_HIP(hipEventSynchronize(b->done_evt), "previous batch");
+        b->pending = false;
+    }
+
+    // alpha for every instance (GPU reductions), one synchronisation
+    for (int i = 0; i < n; ++i) {
+        if ((s = ensure_buffers(gs[i], gs[i]->order == 3)) != HJ_OK) return s;
+        if ((s = launch_alpha_readback(gs[i], st)) != HJ_OK) return s;
+    }
+    HJ_HIP(hipStreamSynchronize(st), "alpha synchronise");
+    // the pinned staging of a previous batch is free once the stream is idle
+
+    std::vector<double> dts(n);
+    std::vector<uint32_t> steps(n), tiles(n);
+    uint32_t max_steps = 0;
+    for (int i = 0; i < n; ++i) {
+        accept_alpha(gs[i]);
+        dts[i] = cfl_dt(gs[i]);
+        std::vector<double> hs;
+        schedule(dts[i], t0[i], tf[i], &hs);
+        steps[i] = uint32_t(hs.size());
+        tiles[i] = uint32_t((gs[i]->total + b->tile_nodes - 1) / b->tile_nodes);
+        max_steps = std::max(max_steps, steps[i]);
+    }
+    const uint32_t order = uint32_t(g0->order);
+    const uint64_t rounds64 = uint64_t(order) * max_steps;
+    if (rounds64 >= (uint64_t(1) << 31)) return fail(HJ_E_ARG, "too many steps");
+    const uint32_t rounds = uint32_t(rounds64);
+    if ((s = reserve(b, uint32_t(n), rounds)) != HJ_OK) return s;
+
+    // instances by step count, descending: the active ones form a prefix
+    std::vector<uint32_t> ord(n);
+    std::iota(ord.begin(), ord.end(), 0u);
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](uint32_t x, uint32_t y) { return steps[x] > steps[y]; });
+    b->h_tile_pre[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        b->h_sorted[k] = ord[k];
+        b->h_tile_pre[k + 1] = b->h_tile_pre[k] + tiles[ord[k]];
+    }
+    uint64_t total = 0;
+    uint32_t active = uint32_t(n);
+    for (uint32_t r = 0; r < rounds; ++r) {
+        while (active > 0 && uint64_t(order) * steps[ord[active - 1]] <= r) --active;
+        b->h_round_off[r] = uint32_t(total);
+        total += b->h_tile_pre[active];
+        if (total >= (uint64_t(1) << 32) - 1) return fail(HJ_E_ARG, "too many work items");
+    }
+    b->h_round_off[rounds] = uint32_t(total);
+
+    const size_t isz = inst_size(g0->prec);
+    for (int i = 0; i < n; ++i) {
+        char *dst = (char *)b->h_inst + isz * i;
+        const bool tube = modes[i] == HJ_TUBE;
+        if (g0->prec == HJ_FP64)
+            fill_inst<double>(dst, gs[i], Vouts[i], V0s[i], dts[i], t0[i], tf[i], tiles[i],
+                              steps[i], tube);
+        else
+            fill_inst<float>(dst, gs[i], Vouts[i], V0s[i], dts[i], t0[i], tf[i], tiles[i],
+                             steps[i], tube);
+    }
+    std::memset(b->h_gl, 0, sizeof(BatchGlobal));
+    b->h_gl->items = uint32_t(total);
+    b->h_gl->rounds = rounds;
+    b->h_gl->ninst = uint32_t(n);
+    b->h_gl->tile_nodes = b->tile_nodes;
+    b->h_gl->order = order;
+
+    HJ_HIP(hipMemcpyAsync(b->inst, b->h_inst, isz * n, hipMemcpyHostToDevice, st), "upload");
+    HJ_HIP(hipMemcpyAsync(b->sorted, b->h_sorted, sizeof(uint32_t) * n, hipMemcpyHostToDevice,
+                          st),
+           "upload");
+    HJ_HIP(hipMemcpyAsync(b->tile_pre, b->h_tile_pre, sizeof(uint32_t) * (n + 1),
+                          hipMemcpyHostToDevice, st),
+           "upload");
+    HJ_HIP(hipMemcpyAsync(b->round_off, b->h_round_off, sizeof(uint32_t) * (rounds + 1),
+                          hipMemcpyHostToDevice, st),
+           "upload");
+    HJ_HIP(hipMemcpyAsync(b->gl, b->h_gl, sizeof(BatchGlobal), hipMemcpyHostToDevice, st),
+           "upload");
+    for (int i = 0; i < n; ++i)
+        HJ_HIP(hipMemcpyAsync(Vouts[i], V0s[i], gs[i]->bytes(), hipMemcpyDeviceToDevice, st),
+               "copy V0");
+    if ((s = run(b, g0->nd, g0->space, g0->dyn, g0->prec, rounds, st)) != HJ_OK) return s;
+    HJ_HIP(hipMemcpyAsync(b->h_ctl_out, b->ctl, sizeof(BatchCtl) * n, hipMemcpyDeviceToHost, st),
+           "read-back");
+    HJ_HIP(hipEventRecord(b->done_evt, st), "batch event");
+    b->pending = true;
+    b->last_n = uint32_t(n);
+    b->last_steps = steps;
+    return HJ_OK;
+}
+
+hj_status hj_batch_wait(hj_batch_t b, void *hip_stream, double *t_final, int64_t *items)
+{
+    if (!b) return fail(HJ_E_ARG, "null batch handle");
+    HJ_HIP(hipStreamSynchronize((hipStream_t)hip_stream), "batch synchronise");
+    if (b->last_n == 0) return fail(HJ_E_STATE, "no batch has been solved");
+    if (items) *items = int64_t(b->h_gl->items);
+    if (t_final)
+        for (uint32_t i = 0; i < b->last_n; ++i)
+            t_final[i] = b->h_ctl_out[i].t[b->last_steps[i] & 1u];
+    return HJ_OK;
+}
+
+hj_status hj_batch_destroy(hj_batch_t b)
+{
+    if (!b) return HJ_OK;
+    (void)hipSetDevice(b->device);
+    if (b->pending) (void)hipEventSynchronize(b->done_evt);
+    drop_graph(b);
+    if (b->done_evt) (void)hipEventDestroy(b->done_evt);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    free_tables(b);
+    if (b->gl) (void)hipFree(b->gl);
+    if (b->h_gl) (void)hipHostFree(b->h_gl);
+    delete b;
+    return HJ_OK;
+}
+
+}  // extern "C"

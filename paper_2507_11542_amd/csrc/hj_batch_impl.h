@@ -1,0 +1,206 @@
+// Batched solve: many independent grids (instances) advanced together, one
+// fused launch per RK-stage round covering every instance still running.
+//
+// Round r is stage r % order of RK step r / order.  The instances are sorted
+// by step count (descending), so the instances still running in round r are
+// a prefix of that order; the round's work is the concatenation of their
+// tiles (tile_nodes nodes each).  The round kernel's workgroups stride over
+// those tiles; the kernel boundary between rounds is the only barrier, so no
+// workgroup ever waits on another.  All rounds are launched back to back (and
+// captured once in a hipGraph by the host), each kernel reading the round
+// tables from device memory.
+//
+// Time: each instance keeps t in FP64 on the device, double-buffered by step
+// parity; the tiles of a step read t_n and use h = min(dt, tf - t_n); tile 0
+// of the step's last stage stores t_n + h into the other slot.
+#pragma once
+
+#include "hj_stage_impl.h"
+
+namespace hj {
+
+template <typename T>
+struct BatchInst {
+    StageArgs<T> geo;  // geometry, tables, alpha, dynamics parameters
+    T *v;              // instance state V (caller's V_out), updated in place
+    T *a;              // stage buffer A
+    T *b;              // stage buffer B
+    const T *v0;       // V0 (tube target)
+    double dt, t0, tf; // CFL step and horizon (FP64)
+    uint32_t tiles;    // items per round
+    uint32_t steps;    // RK steps
+    int tube;
+    int pad;
+};
+
+struct BatchCtl {
+    double t[2];       // t at the start of even / odd steps
+};
+
+struct BatchGlobal {
+    uint32_t items;      // total tiles over all rounds
+    uint32_t rounds;
+    uint32_t ninst;
+    uint32_t tile_nodes;
+    uint32_t order;      // RK order (2 or 3)
+    uint32_t pad[3];
+};
+
+template <typename T>
+struct BatchPtrs {
+    const BatchInst<T> *inst;  // [ninst], original order
+    BatchCtl *ctl;             // [ninst]
+    const uint32_t *sorted;    // [ninst] instance ids by step count, descending
+    const uint32_t *tile_pre;  // [ninst + 1] prefix sums of tiles over `sorted`
+    const uint32_t *round_off; // [rounds + 1] first tile of each round
+    const BatchGlobal *gl;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void batch_init(BatchPtrs<T> p)
+{
+    const uint32_t n = p.gl->ninst;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        p.ctl[i].t[0] = p.inst[i].t0;
+        p.ctl[i].t[1] = p.inst[i].t0;
+    }
+}
+
+// largest k in [0, n) with a[k] <= x (a[0] <= x, a ascending)
+__device__ inline uint32_t upper_index(const uint32_t *a, uint32_t n, uint32_t x)
+{
+    uint32_t lo = 0, hi = n;  // invariant: a[lo] <= x, answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, int D, int SCH, int DYN>
+__global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r)
+{
+    if (r >= p.gl->rounds) return;  // rounds beyond this batch: nothing to do
+    const uint32_t begin = p.round_off[r], end = p.round_off[r + 1];
+    const uint32_t order = p.gl->order;
+    const uint32_t stage = r % order, step = r / order;
+    const uint32_t tn = p.gl->tile_nodes;
+    for (uint32_t k = begin + blockIdx.x; k < end; k += gridDim.x) {
+        const uint32_t local = k - begin;
+        const uint32_t s = upper_index(p.tile_pre, p.gl->ninst, local);
+        const uint32_t inst = __builtin_amdgcn_readfirstlane(p.sorted[s]);
+        const uint32_t tile = __builtin_amdgcn_readfirstlane(local - p.tile_pre[s]);
+        const BatchInst<T> &in = p.inst[inst];
+        const double t_n = p.ctl[inst].t[step & 1u];
+        const double rem = in.tf - t_n;
+        const double h = in.dt < rem ? in.dt : rem;
+        StageArgs<T> a = in.geo;
+        a.dt = T(h);
+        a.v0 = in.v0;
+        a.tube = 0;
+        if (stage == 0) {
+            a.vs = in.v;
+            a.vb = nullptr;
+            a.out = in.a;
+            a.combine = kEuler;
+        } else if (stage == 1 && order == 3) {
+            a.vs = in.a;
+            a.vb = in.v;
+            a.out = in.b;
+            a.combine = kBlend;
+            a.wb = T(3);
+            a.w2 = T(1);
+            a.den = T(4);
+        } else if (order == 2) {
+            a.vs = in.a;
+            a.vb = in.v;
+            a.out = in.v;
+            a.combine = kBlend;
+            a.wb = T(1);
+            a.w2 = T(1);
+            a.den = T(2);
+            a.tube = in.tube;
+        } else {
+            a.vs = in.b;
+            a.vb = in.v;
+            a.out = in.v;
+            a.combine = kBlend;
+            a.wb = T(1);
+            a.w2 = T(2);
+            a.den = T(3);
+            a.tube = in.tube;
+        }
+        const uint32_t first = tile * tn;
+        const uint32_t last = first + tn < a.total ? first + tn : a.total;
+        for (uint32_t node = first + threadIdx.x; node < last; node += 256)
+            stage_node<T, D, SCH, DYN>(a, node);
+        // the other slot: read by no tile of this step
+        if (stage == order - 1 && tile == 0 && threadIdx.x == 0)
+            p.ctl[inst].t[(step + 1) & 1u] = t_n + h;
+    }
+}
+
+// The init kernel and rounds [0, rounds) of the round kernel, back to back.
+template <typename T, int D, int SCH, int DYN>
+hipError_t batch_launch_one(const BatchPtrs<T> &p, uint32_t rounds, uint32_t workgroups,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_init<T>), dim3(1), dim3(256), 0, s, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (uint32_t r = 0; r < rounds; ++r) {
+        hipLaunchKernelGGL((batch_round<T, D, SCH, DYN>), dim3(workgroups), dim3(256), 0, s, p,
+                           r);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, int D, int DYN>
+hipError_t batch_launch_space(int space, const BatchPtrs<T> &p, uint32_t rounds, uint32_t wg,
+                              hipStream_t s)
+{
+    if (space == kEno2) return batch_launch_one<T, D, kEno2, DYN>(p, rounds, wg, s);
+    if (space == kWeno5) return batch_launch_one<T, D, kWeno5, DYN>(p, rounds, wg, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t batch_launch_t(int ndim, int space, int dyn, const BatchPtrs<T> &p, uint32_t rounds,
+                          uint32_t wg, hipStream_t s)
+{
+    switch (dyn) {
+    case kTranslation:
+        switch (ndim) {
+        case 1: return batch_launch_space<T, 1, kTranslation>(space, p, rounds, wg, s);
+        case 2: return batch_launch_space<T, 2, kTranslation>(space, p, rounds, wg, s);
+        case 3: return batch_launch_space<T, 3, kTranslation>(space, p, rounds, wg, s);
+        case 4: return batch_launch_space<T, 4, kTranslation>(space, p, rounds, wg, s);
+        }
+        break;
+    case kBall:
+        switch (ndim) {
+        case 1: return batch_launch_space<T, 1, kBall>(space, p, rounds, wg, s);
+        case 2: return batch_launch_space<T, 2, kBall>(space, p, rounds, wg, s);
+        case 3: return batch_launch_space<T, 3, kBall>(space, p, rounds, wg, s);
+        case 4: return batch_launch_space<T, 4, kBall>(space, p, rounds, wg, s);
+        }
+        break;
+    case kDoubleIntegrator:
+        if (ndim == 2) return batch_launch_space<T, 2, kDoubleIntegrator>(space, p, rounds, wg, s);
+        break;
+    case kRelDubins:
+        if (ndim == 3) return batch_launch_space<T, 3, kRelDubins>(space, p, rounds, wg, s);
+        break;
+    case kDubins4D:
+        if (ndim == 4) return batch_launch_space<T, 4, kDubins4D>(space, p, rounds, wg, s);
+        break;
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hj

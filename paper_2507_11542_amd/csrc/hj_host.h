@@ -1,0 +1,72 @@
+// Host-side internals of libhj shared by the single-solve and batch
+// entry points (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hj.h"
+#include "hj_internal.h"
+
+struct hj_grid_s {
+    int nd = 0;
+    int64_t n[hj::kMaxDim] = {1, 1, 1, 1};
+    double lo[hj::kMaxDim] = {0, 0, 0, 0}, hi[hj::kMaxDim] = {0, 0, 0, 0};
+    double dx[hj::kMaxDim] = {1, 1, 1, 1};
+    uint32_t pmask = 0;
+    hj_precision prec = HJ_FP64;
+    int64_t total = 0;
+    uint32_t stride[hj::kMaxDim] = {0, 0, 0, 0};
+    uint32_t tab_off[hj::kMaxDim] = {0, 0, 0, 0};
+    int device = 0;
+
+    int dyn = -1;
+    double prm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+    int space = HJ_WENO5;
+    int order = 3;
+    double cfl = 0.8;
+
+    double *tab64 = nullptr;   // device, FP64 tables (alpha and FP64 stages)
+    float *tab32 = nullptr;    // device, FP32 tables (FP32 stages)
+    void *bufA = nullptr;      // stage buffers
+    void *bufB = nullptr;
+    double *partial = nullptr; // alpha pass-1 partial maxima
+    double *alpha_dev = nullptr;
+    double *alpha_host = nullptr;  // pinned
+    bool alpha_valid = false;
+    double alpha[hj::kMaxDim] = {0, 0, 0, 0};
+
+    size_t elem() const { return prec == HJ_FP64 ? sizeof(double) : sizeof(float); }
+    size_t bytes() const { return size_t(total) * elem(); }
+};
+
+namespace hj {
+
+hj_status fail(hj_status s, const std::string &msg);
+hj_status hip_fail(hipError_t e, const char *what);
+hj_status dev_alloc(void **p, size_t bytes, const char *what);
+hj_status use_device(hj_grid_t g);
+hj_status ensure_buffers(hj_grid_t g, bool need_b);
+hj_status check_ready(hj_grid_t g);
+// Enqueue the alpha reduction and its read-back into pinned memory.
+hj_status launch_alpha_readback(hj_grid_t g, hipStream_t s);
+// After the stream has synchronised: take the read-back alpha.
+void accept_alpha(hj_grid_t g);
+hj_status compute_alpha(hj_grid_t g, hipStream_t s);
+double cfl_dt(hj_grid_t g);
+void schedule(double dt, double t0, double tf, std::vector<double> *hs);
+extern const double kEpsT;
+template <typename T>
+StageArgs<T> base_args(hj_grid_t g);
+
+}  // namespace hj
+
+#define HJ_HIP(call, what)                                       \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hj::hip_fail(e_, (what));   \
+    } while (0)

@@ -60,8 +60,15 @@ def _load():
     lib.hj_rhs.argtypes = [P, P, P, P]
     lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
     lib.hj_grid_destroy.argtypes = [P]
+    lib.hj_batch_create.argtypes = [ctypes.POINTER(P)]
+    lib.hj_batch_config.argtypes = [P, I, I, I]
+    lib.hj_solve_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(P),
+                                   ctypes.POINTER(P), PD, PD, ctypes.POINTER(I), P]
+    lib.hj_batch_wait.argtypes = [P, P, PD, PI64]
+    lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
-                 "hj_rhs", "hj_get_schedule", "hj_grid_destroy"):
+                 "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_batch_create",
+                 "hj_batch_config", "hj_solve_batch", "hj_batch_wait", "hj_batch_destroy"):
         getattr(lib, name).restype = I
     lib.hj_last_error.argtypes = []
     lib.hj_last_error.restype = ctypes.c_char_p
@@ -157,6 +164,70 @@ def hj_get_schedule(g, t0: float, tf: float, ndim: int, stream=None):
 
 def hj_grid_destroy(g):
     _check(_lib.hj_grid_destroy(g))
+
+
+def hj_batch_create() -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(_lib.hj_batch_create(ctypes.byref(h)))
+    return h
+
+
+def hj_batch_config(b, tile_nodes: int = 4096, workgroups: int = 1024, use_graph: bool = True):
+    _check(_lib.hj_batch_config(b, int(tile_nodes), int(workgroups), 1 if use_graph else 0))
+
+
+def hj_solve_batch(b, grids, V0s, Vouts, t0s, tfs, modes, stream=None):
+    n = len(grids)
+    P = ctypes.c_void_p
+    ga = (P * n)(*[g.value if isinstance(g, ctypes.c_void_p) else g for g in grids])
+    va = (P * n)(*[_ptr(v) for v in V0s])
+    oa = (P * n)(*[_ptr(v) for v in Vouts])
+    ta = (ctypes.c_double * n)(*[float(t) for t in t0s])
+    fa = (ctypes.c_double * n)(*[float(t) for t in tfs])
+    ma = (ctypes.c_int * n)(*[int(m) for m in modes])
+    _check(_lib.hj_solve_batch(b, n, ga, va, oa, ta, fa, ma, _stream(stream)))
+
+
+def hj_batch_wait(b, n: int, stream=None):
+    """Waits for the last batch; returns (final times, work items)."""
+    tf = (ctypes.c_double * max(1, n))()
+    items = ctypes.c_int64(0)
+    _check(_lib.hj_batch_wait(b, _stream(stream), tf, ctypes.byref(items)))
+    return [tf[k] for k in range(n)], items.value
+
+
+def hj_batch_destroy(b):
+    _check(_lib.hj_batch_destroy(b))
+
+
+class Batch:
+    """Owning wrapper of one hj_batch_t (marshalling only)."""
+
+    def __init__(self, tile_nodes=4096, workgroups=1024, use_graph=True):
+        self.handle = hj_batch_create()
+        self.config(tile_nodes, workgroups, use_graph)
+
+    def config(self, tile_nodes=4096, workgroups=1024, use_graph=True):
+        self.tile_nodes, self.workgroups, self.use_graph = tile_nodes, workgroups, use_graph
+        hj_batch_config(self.handle, tile_nodes, workgroups, use_graph)
+
+    def solve(self, grids, V0s, Vouts, t0s, tfs, modes, stream=None):
+        hj_solve_batch(self.handle, [g.handle for g in grids], V0s, Vouts, t0s, tfs,
+                       [MODE[m] if isinstance(m, str) else m for m in modes], stream)
+
+    def wait(self, n, stream=None):
+        return hj_batch_wait(self.handle, n, stream)
+
+    def close(self):
+        if self.handle is not None:
+            hj_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Grid:
