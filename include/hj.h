@@ -159,7 +159,23 @@ hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *c
                          void *const *Vouts, const double *t0, const double *tf,
                          const hj_mode *modes, void *hip_stream);
 
-/* Waits for the last hj_solve_batch on hip_stream.  t_final (n doubles, may
+/* Resumable batched stepping (the continuous-batching form): instance i
+ * advances Vs[i] in place by up to max_steps TVD-RK steps (all remaining
+ * steps if max_steps <= 0) from the time t[i] toward tf[i]; the step sequence
+ * and termination rule are those of a solve started at t0[i], so any split
+ * into calls gives the hj_solve result bit for bit.  On return t[i] holds the
+ * time reached (computed on the host in FP64 exactly as the device
+ * accumulates it), steps_taken[i] (may be NULL) the number of steps taken
+ * and finished[i] (may be NULL) is 1 when tf[i] is reached.
+ * V0s[i] is read for HJ_TUBE instances (may be NULL for HJ_SET ones; V0s may
+ * be NULL when no instance is a tube).  alpha is reduced on an instance's
+ * first call and cached in its grid.  Enqueues on hip_stream and returns. */
+hj_status hj_step_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
+                        void *const *Vs, const double *t0, double *t, const double *tf,
+                        const hj_mode *modes, int max_steps, int *steps_taken, int *finished,
+                        void *hip_stream);
+
+/* Waits for the last hj_solve_batch or hj_step_batch on hip_stream.  t_final (n doubles, may
  * be NULL) receives each instance's device-accumulated final time, items
  * (may be NULL) the number of tiles over all rounds.  The grids passed to
  * hj_solve_batch must stay alive until this returns. */
@@ -167,6 +183,13 @@ hj_status hj_batch_wait(hj_batch_t b, void *hip_stream, double *t_final, int64_t
 
 /* Frees the engine (waits for its last batch).  NULL is accepted. */
 hj_status hj_batch_destroy(hj_batch_t b);
+
+/* Caller-owned stage buffers: A and B are device arrays of prod(N) elements
+ * of the grid's element type, not overlapping each other or any V passed to
+ * this grid's solves; the handle uses them instead of allocating its own
+ * (freeing any it had) and never frees them.  For callers that keep device
+ * memory in their own pool (a serving loop). */
+hj_status hj_grid_set_workspace(hj_grid_t g, void *A, void *B);
 
 /* Frees the handle, its tables and stage buffers (after the device is idle
  * for this handle's work).  NULL is accepted. */

@@ -463,14 +463,30 @@ hj_status hj_rhs(hj_grid_t g, const void *V, void *L_out, void *hip_stream)
     return stage<float>(g, V, nullptr, nullptr, L_out, kRhs, 0, 0, 0, 1, false, st);
 }
 
+hj_status hj_grid_set_workspace(hj_grid_t g, void *A, void *B)
+{
+    if (!g) return fail(HJ_E_ARG, "null grid handle");
+    if (!A || !B) return fail(HJ_E_ARG, "workspace buffers must be non-NULL");
+    if (overlap(A, B, g->bytes())) return fail(HJ_E_ARG, "workspace buffers overlap");
+    if ((hj_status)use_device(g) != HJ_OK) return HJ_E_DEVICE;
+    if (g->own_bufs) {
+        if (g->bufA) (void)hipFree(g->bufA);
+        if (g->bufB) (void)hipFree(g->bufB);
+    }
+    g->bufA = A;
+    g->bufB = B;
+    g->own_bufs = false;
+    return HJ_OK;
+}
+
 hj_status hj_grid_destroy(hj_grid_t g)
 {
     if (!g) return HJ_OK;
     (void)hipSetDevice(g->device);
     if (g->tab64) (void)hipFree(g->tab64);
     if (g->tab32) (void)hipFree(g->tab32);
-    if (g->bufA) (void)hipFree(g->bufA);
-    if (g->bufB) (void)hipFree(g->bufB);
+    if (g->own_bufs && g->bufA) (void)hipFree(g->bufA);
+    if (g->own_bufs && g->bufB) (void)hipFree(g->bufB);
     if (g->partial) (void)hipFree(g->partial);
     if (g->alpha_dev) (void)hipFree(g->alpha_dev);
     if (g->alpha_host) (void)hipHostFree(g->alpha_host);

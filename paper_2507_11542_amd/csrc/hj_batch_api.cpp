@@ -270,12 +270,22 @@ hj_status hj_batch_config(hj_batch_t b, int tile_nodes, int workgroups, int use_
     return HJ_OK;
 }
 
-hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
-                         void *const *Vouts, const double *t0, const double *tf,
-                         const hj_mode *modes, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// Shared body of hj_solve_batch and hj_step_batch: instance i advances V[i]
+// in place by up to max_steps RK steps (all remaining steps if max_steps <= 0)
+// from time tcur[i] toward tf[i], with the termination rule taken relative to
+// its original start t0[i].  copy_v0: V[i] <- V0[i] first (a fresh solve).
+// fresh_alpha: reduce alpha again even where the handle has it cached.
+hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
+                    void *const *Vs, const double *t0, const double *tcur, const double *tf,
+                    const hj_mode *modes, int64_t max_steps, bool copy_v0, bool fresh_alpha,
+                    double *t_reached, hipStream_t st)
 {
     if (!b) return fail(HJ_E_ARG, "null batch handle");
-    if (n < 1 || !gs || !V0s || !Vouts || !t0 || !tf || !modes)
+    if (n < 1 || !gs || !Vs || !t0 || !tcur || !tf || !modes)
         return fail(HJ_E_ARG, "need n >= 1 and non-NULL arrays");
     hj_status s;
     const hj_grid_t g0 = gs[0];
@@ -286,49 +296,65 @@ hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *c
             g->order != g0->order || g->prec != g0->prec || g->device != b->device)
             return fail(HJ_E_ARG, "instances must share ndim, dynamics, scheme, RK order, "
                                   "precision and device");
-        if (!V0s[i] || !Vouts[i]) return fail(HJ_E_ARG, "NULL V0 or V_out");
         if (modes[i] != HJ_SET && modes[i] != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
-        if (!(std::isfinite(t0[i]) && std::isfinite(tf[i]) && tf[i] >= t0[i]))
-            return fail(HJ_E_ARG, "need finite t0 <= tf");
-        if (overlap(V0s[i], g->bytes(), Vouts[i], g->bytes()))
-            return fail(HJ_E_ARG, "V_out overlaps V0 for instance " + std::to_string(i));
-        for (int j = 0; j < i; ++j)
-            if (overlap(Vouts[i], g->bytes(), Vouts[j], gs[j]->bytes()) ||
-                overlap(Vouts[i], g->bytes(), V0s[j], gs[j]->bytes()))
+        const void *v0 = V0s ? V0s[i] : nullptr;
+        if (!Vs[i] || ((copy_v0 || modes[i] == HJ_TUBE) && !v0))
+            return fail(HJ_E_ARG, "NULL V, or NULL V0 where it is read");
+        if (!(std::isfinite(t0[i]) && std::isfinite(tcur[i]) && std::isfinite(tf[i]) &&
+              tf[i] >= t0[i] && tcur[i] >= t0[i]))
+            return fail(HJ_E_ARG, "need finite t0 <= t and t0 <= tf");
+        if (v0 && overlap(v0, g->bytes(), Vs[i], g->bytes()))
+            return fail(HJ_E_ARG, "V overlaps V0 for instance " + std::to_string(i));
+        for (int j = 0; j < i; ++j) {
+            const void *w0 = V0s ? V0s[j] : nullptr;
+            if (overlap(Vs[i], g->bytes(), Vs[j], gs[j]->bytes()) ||
+                (w0 && overlap(Vs[i], g->bytes(), w0, gs[j]->bytes())))
                 return fail(HJ_E_ARG, "instances " + std::to_string(j) + " and " +
                                           std::to_string(i) + " share memory");
+        }
     }
     if (g0->space == HJ_UPWIND1 || g0->order == 1)
         return fail(HJ_E_UNSUPPORTED, "batched solves support ENO2/WENO5 with RK2/RK3");
-    hipStream_t st = (hipStream_t)hip_stream;
     HJ_HIP(hipSetDevice(b->device), "hipSetDevice");
     if (b->pending) {
         HJ_HIP(hipEventSynchronize(b->done_evt), "previous batch");
         b->pending = false;
     }
 
-    // alpha for every instance (GPU reductions), one synchronisation
+    // alpha for every instance that needs it (GPU reductions), one wait
+    bool any = false;
     for (int i = 0; i < n; ++i) {
         if ((s = ensure_buffers(gs[i], gs[i]->order == 3)) != HJ_OK) return s;
-        if ((s = launch_alpha_readback(gs[i], st)) != HJ_OK) return s;
+        if (fresh_alpha || !gs[i]->alpha_valid) {
+            if ((s = launch_alpha_readback(gs[i], st)) != HJ_OK) return s;
+            gs[i]->alpha_valid = false;
+            any = true;
+        }
     }
-    HJ_HIP(hipStreamSynchronize(st), "alpha synchronise");
-    // the pinned staging of a previous batch is free once the stream is idle
+    if (any) HJ_HIP(hipStreamSynchronize(st), "alpha synchronise");
 
     std::vector<double> dts(n);
     std::vector<uint32_t> steps(n), tiles(n);
-    uint32_t max_steps = 0;
+    uint32_t max_n = 0;
     for (int i = 0; i < n; ++i) {
-        accept_alpha(gs[i]);
+        if (!gs[i]->alpha_valid) accept_alpha(gs[i]);
         dts[i] = cfl_dt(gs[i]);
-        std::vector<double> hs;
-        schedule(dts[i], t0[i], tf[i], &hs);
-        steps[i] = uint32_t(hs.size());
+        // the Sec. 5 loop from the current time, relative rule as for a solve
+        double t = tcur[i];
+        uint32_t k = 0;
+        if (tf[i] > t0[i])
+            while (tf[i] - t >= kEpsT * (tf[i] - t0[i]) && (max_steps <= 0 || k < max_steps)) {
+                const double h = dts[i] < tf[i] - t ? dts[i] : tf[i] - t;
+                t = t + h;
+                ++k;
+            }
+        steps[i] = k;
+        if (t_reached) t_reached[i] = t;
         tiles[i] = uint32_t((gs[i]->total + b->tile_nodes - 1) / b->tile_nodes);
-        max_steps = std::max(max_steps, steps[i]);
+        max_n = std::max(max_n, steps[i]);
     }
     const uint32_t order = uint32_t(g0->order);
-    const uint64_t rounds64 = uint64_t(order) * max_steps;
+    const uint64_t rounds64 = uint64_t(order) * max_n;
     if (rounds64 >= (uint64_t(1) << 31)) return fail(HJ_E_ARG, "too many steps");
     const uint32_t rounds = uint32_t(rounds64);
     if ((s = reserve(b, uint32_t(n), rounds)) != HJ_OK) return s;
@@ -357,12 +383,13 @@ hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *c
     for (int i = 0; i < n; ++i) {
         char *dst = (char *)b->h_inst + isz * i;
         const bool tube = modes[i] == HJ_TUBE;
+        const void *v0 = V0s ? V0s[i] : nullptr;
         if (g0->prec == HJ_FP64)
-            fill_inst<double>(dst, gs[i], Vouts[i], V0s[i], dts[i], t0[i], tf[i], tiles[i],
-                              steps[i], tube);
+            fill_inst<double>(dst, gs[i], Vs[i], v0, dts[i], tcur[i], tf[i], tiles[i], steps[i],
+                              tube);
         else
-            fill_inst<float>(dst, gs[i], Vouts[i], V0s[i], dts[i], t0[i], tf[i], tiles[i],
-                             steps[i], tube);
+            fill_inst<float>(dst, gs[i], Vs[i], v0, dts[i], tcur[i], tf[i], tiles[i], steps[i],
+                             tube);
     }
     std::memset(b->h_gl, 0, sizeof(BatchGlobal));
     b->h_gl->items = uint32_t(total);
@@ -383,9 +410,10 @@ hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *c
            "upload");
     HJ_HIP(hipMemcpyAsync(b->gl, b->h_gl, sizeof(BatchGlobal), hipMemcpyHostToDevice, st),
            "upload");
-    for (int i = 0; i < n; ++i)
-        HJ_HIP(hipMemcpyAsync(Vouts[i], V0s[i], gs[i]->bytes(), hipMemcpyDeviceToDevice, st),
-               "copy V0");
+    if (copy_v0)
+        for (int i = 0; i < n; ++i)
+            HJ_HIP(hipMemcpyAsync(Vs[i], V0s[i], gs[i]->bytes(), hipMemcpyDeviceToDevice, st),
+                   "copy V0");
     if ((s = run(b, g0->nd, g0->space, g0->dyn, g0->prec, rounds, st)) != HJ_OK) return s;
     HJ_HIP(hipMemcpyAsync(b->h_ctl_out, b->ctl, sizeof(BatchCtl) * n, hipMemcpyDeviceToHost, st),
            "read-back");
@@ -393,6 +421,37 @@ hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *c
     b->pending = true;
     b->last_n = uint32_t(n);
     b->last_steps = steps;
+    return HJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
+                         void *const *Vouts, const double *t0, const double *tf,
+                         const hj_mode *modes, void *hip_stream)
+{
+    if (!V0s) return fail(HJ_E_ARG, "V0s is NULL");
+    return batch_run(b, n, gs, V0s, Vouts, t0, t0, tf, modes, 0, true, true, nullptr,
+                     (hipStream_t)hip_stream);
+}
+
+hj_status hj_step_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
+                        void *const *Vs, const double *t0, double *t, const double *tf,
+                        const hj_mode *modes, int max_steps, int *steps_taken, int *finished,
+                        void *hip_stream)
+{
+    if (!t) return fail(HJ_E_ARG, "t is NULL");
+    std::vector<double> reached(n > 0 ? n : 1);
+    hj_status s = batch_run(b, n, gs, V0s, Vs, t0, t, tf, modes, max_steps, false, false,
+                            reached.data(), (hipStream_t)hip_stream);
+    if (s != HJ_OK) return s;
+    for (int i = 0; i < n; ++i) {
+        t[i] = reached[i];
+        if (steps_taken) steps_taken[i] = int(b->last_steps[i]);
+        if (finished) finished[i] = !(tf[i] > t0[i] && tf[i] - t[i] >= kEpsT * (tf[i] - t0[i]));
+    }
     return HJ_OK;
 }
 

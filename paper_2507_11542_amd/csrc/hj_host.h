@@ -34,6 +34,7 @@ struct hj_grid_s {
     float *tab32 = nullptr;    // device, FP32 tables (FP32 stages)
     void *bufA = nullptr;      // stage buffers
     void *bufB = nullptr;
+    bool own_bufs = true;      // false after hj_grid_set_workspace
     double *partial = nullptr; // alpha pass-1 partial maxima
     double *alpha_dev = nullptr;
     double *alpha_host = nullptr;  // pinned

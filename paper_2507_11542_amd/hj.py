@@ -60,15 +60,21 @@ def _load():
     lib.hj_rhs.argtypes = [P, P, P, P]
     lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
     lib.hj_grid_destroy.argtypes = [P]
+    lib.hj_grid_set_workspace.argtypes = [P, P, P]
     lib.hj_batch_create.argtypes = [ctypes.POINTER(P)]
     lib.hj_batch_config.argtypes = [P, I, I, I]
     lib.hj_solve_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(P),
                                    ctypes.POINTER(P), PD, PD, ctypes.POINTER(I), P]
+    lib.hj_step_batch.argtypes = [P, I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                  PD, PD, PD, ctypes.POINTER(I), I, ctypes.POINTER(I),
+                                  ctypes.POINTER(I), P]
     lib.hj_batch_wait.argtypes = [P, P, PD, PI64]
     lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
-                 "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_batch_create",
-                 "hj_batch_config", "hj_solve_batch", "hj_batch_wait", "hj_batch_destroy"):
+                 "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_grid_set_workspace",
+                 "hj_batch_create",
+                 "hj_batch_config", "hj_solve_batch", "hj_step_batch", "hj_batch_wait",
+                 "hj_batch_destroy"):
         getattr(lib, name).restype = I
     lib.hj_last_error.argtypes = []
     lib.hj_last_error.restype = ctypes.c_char_p
@@ -166,6 +172,10 @@ def hj_grid_destroy(g):
     _check(_lib.hj_grid_destroy(g))
 
 
+def hj_grid_set_workspace(g, A, B):
+    _check(_lib.hj_grid_set_workspace(g, _ptr(A), _ptr(B)))
+
+
 def hj_batch_create() -> ctypes.c_void_p:
     h = ctypes.c_void_p()
     _check(_lib.hj_batch_create(ctypes.byref(h)))
@@ -186,6 +196,26 @@ def hj_solve_batch(b, grids, V0s, Vouts, t0s, tfs, modes, stream=None):
     fa = (ctypes.c_double * n)(*[float(t) for t in tfs])
     ma = (ctypes.c_int * n)(*[int(m) for m in modes])
     _check(_lib.hj_solve_batch(b, n, ga, va, oa, ta, fa, ma, _stream(stream)))
+
+
+def hj_step_batch(b, grids, V0s, Vs, t0s, ts, tfs, modes, max_steps, stream=None):
+    """Advances each instance in place by up to max_steps steps from ts[i];
+    returns (new times, steps taken, finished flags)."""
+    n = len(grids)
+    P = ctypes.c_void_p
+    ga = (P * n)(*[g.value if isinstance(g, ctypes.c_void_p) else g for g in grids])
+    va = (P * n)(*[_ptr(v) for v in V0s]) if V0s is not None else None
+    oa = (P * n)(*[_ptr(v) for v in Vs])
+    t0a = (ctypes.c_double * n)(*[float(t) for t in t0s])
+    ta = (ctypes.c_double * n)(*[float(t) for t in ts])
+    fa = (ctypes.c_double * n)(*[float(t) for t in tfs])
+    ma = (ctypes.c_int * n)(*[int(m) for m in modes])
+    taken = (ctypes.c_int * n)()
+    done = (ctypes.c_int * n)()
+    _check(_lib.hj_step_batch(b, n, ga, va, oa, t0a, ta, fa, ma, int(max_steps), taken, done,
+                              _stream(stream)))
+    return ([ta[k] for k in range(n)], [taken[k] for k in range(n)],
+            [bool(done[k]) for k in range(n)])
 
 
 def hj_batch_wait(b, n: int, stream=None):
@@ -214,6 +244,11 @@ class Batch:
     def solve(self, grids, V0s, Vouts, t0s, tfs, modes, stream=None):
         hj_solve_batch(self.handle, [g.handle for g in grids], V0s, Vouts, t0s, tfs,
                        [MODE[m] if isinstance(m, str) else m for m in modes], stream)
+
+    def step(self, grids, V0s, Vs, t0s, ts, tfs, modes, max_steps, stream=None):
+        return hj_step_batch(self.handle, [g.handle for g in grids], V0s, Vs, t0s, ts, tfs,
+                             [MODE[m] if isinstance(m, str) else m for m in modes], max_steps,
+                             stream)
 
     def wait(self, n, stream=None):
         return hj_batch_wait(self.handle, n, stream)
@@ -261,6 +296,10 @@ class Grid:
 
     def rhs(self, V, L_out, stream=None):
         hj_rhs(self.handle, V, L_out, stream)
+
+    def set_workspace(self, A, B):
+        hj_grid_set_workspace(self.handle, A, B)
+        self._workspace = (A, B)  # keep the tensors alive with the grid
 
     def schedule(self, t0, tf, stream=None):
         return hj_get_schedule(self.handle, t0, tf, len(self.n), stream)

@@ -1,0 +1,304 @@
+"""Continuous-batching request server for level-set solves on one GPU.
+
+Requests (a Problem: grid, dynamics, scheme, horizon, V0 recipe) arrive over
+time.  The server admits a request when it has arrived, a slot is free and
+its device bytes fit the HBM budget, and keeps every admitted solve resident
+on the device until it finishes.  Admitted requests are grouped by kernel
+family (ndim, dynamics, scheme, RK order, precision); every macro-iteration
+advances each family by up to `macro_steps` RK steps per instance with one
+batched launch sequence (hj_step_batch, replayed from one captured graph), the
+families on their own streams so their work overlaps on the device.  After a
+macro-iteration finished requests retire (their memory returns to the budget)
+and waiting requests join: requests arriving while others are on the GPU are
+admitted as slots and memory free up.
+
+Scheduling is separate from the device: `Server` drives a backend with
+`bytes_needed / admit / advance / sync / release`; `GpuBackend` implements it
+with libhj through its C ABI (torch for device memory and streams).  The
+per-request results equal those of a request solved alone (the batched kernels
+run the same per-node arithmetic with the same FP64 step sizes).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import inputs
+
+
+@dataclasses.dataclass
+class Job:
+    rid: int
+    problem: inputs.Problem
+    arrival: float
+    t: float = 0.0
+    state: str = "pending"       # pending | active | done | rejected
+    reason: str = ""
+    admitted_at: Optional[float] = None
+    finished_at: Optional[float] = None
+    nbytes: int = 0
+    steps_done: int = 0
+    dev_finished: bool = False   # set by the backend after each advance
+    result: Optional[np.ndarray] = None
+    dev: object = None           # backend state
+
+    @property
+    def key(self) -> Tuple:
+        p = self.problem
+        return (p.ndim, p.dynamics, p.scheme, p.order)
+
+    @property
+    def latency(self) -> Optional[float]:
+        if self.finished_at is None:
+            return None
+        return self.finished_at - self.arrival
+
+
+@dataclasses.dataclass
+class ServeReport:
+    requests: int
+    completed: int
+    rejected: int
+    makespan_s: float
+    updates: float
+    updates_per_s: float
+    p50_s: float
+    p99_s: float
+    mean_s: float
+    max_active: int
+    peak_bytes: int
+    macro_iterations: int
+
+    def as_dict(self):
+        return dataclasses.asdict(self)
+
+
+def percentile(xs: Sequence[float], q: float) -> float:
+    if not xs:
+        return float("nan")
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def report(jobs: List[Job], makespan: float, max_active: int, peak: int, iters: int,
+           updates: float) -> ServeReport:
+    lat = [j.latency for j in jobs if j.state == "done"]
+    return ServeReport(len(jobs), len(lat), sum(j.state == "rejected" for j in jobs), makespan,
+                       updates, updates / makespan if makespan > 0 else 0.0,
+                       percentile(lat, 50), percentile(lat, 99),
+                       float(np.mean(lat)) if lat else float("nan"), max_active, peak, iters)
+
+
+class Server:
+    """Admission by device bytes and slots, continuous batching by family."""
+
+    def __init__(self, backend, hbm_budget: int, max_active: int = 256, macro_steps: int = 32,
+                 clock=time.perf_counter, sleep=time.sleep):
+        self.backend = backend
+        self.hbm_budget = int(hbm_budget)
+        self.max_active = int(max_active)
+        self.macro_steps = int(macro_steps)
+        self.clock = clock
+        self.sleep = sleep
+
+    def run(self, requests: Sequence[inputs.Request], keep_results: bool = False
+            ) -> Tuple[ServeReport, List[Job]]:
+        jobs = [Job(k, r.problem, r.arrival, t=r.problem.t0) for k, r in enumerate(requests)]
+        pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.rid)))
+        active: Dict[Tuple, List[Job]] = collections.OrderedDict()
+        used = 0
+        n_active = 0
+        max_active = peak = iters = 0
+        updates = 0.0
+        start = self.clock()
+        while pending or n_active:
+            now = self.clock() - start
+            # admission: arrived, slot free, bytes fit (arrival order)
+            while pending and pending[0].arrival <= now:
+                j = pending[0]
+                need = self.backend.bytes_needed(j)
+                if need > self.hbm_budget:
+                    pending.popleft()
+                    j.state, j.reason = "rejected", "needs %d bytes > budget" % need
+                    continue
+                if used + need > self.hbm_budget or n_active >= self.max_active:
+                    break
+                pending.popleft()
+                try:
+                    self.backend.admit(j)
+                except MemoryError as e:
+                    j.state, j.reason = "rejected", "allocation failed: %s" % e
+                    continue
+                j.nbytes = need
+                j.state = "active"
+                j.admitted_at = now
+                used += need
+                n_active += 1
+                active.setdefault(j.key, []).append(j)
+            max_active = max(max_active, n_active)
+            peak = max(peak, used)
+            if not n_active:
+                if pending:
+                    wait = pending[0].arrival - (self.clock() - start)
+                    if wait > 0:
+                        self.sleep(min(wait, 0.05))
+                continue
+            # one macro-iteration: every family advances, on its own stream
+            for key, group in active.items():
+                self.backend.advance(key, group, self.macro_steps)
+            for key in list(active):
+                self.backend.sync(key)
+            iters += 1
+            done_at = self.clock() - start
+            for key in list(active):
+                group = active[key]
+                keep = []
+                for j in group:
+                    if j.dev_finished:
+                        if keep_results:
+                            j.result = self.backend.result(j)
+                        updates += float(j.problem.points) * j.steps_done
+                        self.backend.release(j)
+                        j.state = "done"
+                        j.finished_at = done_at
+                        used -= j.nbytes
+                        n_active -= 1
+                    else:
+                        keep.append(j)
+                if keep:
+                    active[key] = keep
+                else:
+                    del active[key]
+                    self.backend.idle(key)
+        makespan = self.clock() - start
+        return report(jobs, makespan, max_active, peak, iters, updates), jobs
+
+
+class GpuBackend:
+    """libhj through its C ABI; torch supplies device memory and streams."""
+
+    def __init__(self, prec: str = "fp32", tile_nodes: int = 4096, workgroups: int = 1024,
+                 use_graph: bool = True, v0_cache: Optional[Dict[int, np.ndarray]] = None):
+        import torch
+
+        from . import hj
+
+        self.torch = torch
+        self.hj = hj
+        self.prec = prec
+        self.dtype = torch.float32 if prec == "fp32" else torch.float64
+        self.elem = 4 if prec == "fp32" else 8
+        self.cfg = (tile_nodes, workgroups, use_graph)
+        self.v0_cache = v0_cache if v0_cache is not None else {}
+        self.engines: Dict[Tuple, object] = {}
+        self.streams: Dict[Tuple, object] = {}
+        self.device = torch.device("cuda")
+
+    def bytes_needed(self, j: Job) -> int:
+        # V0, V and two stage buffers, plus the coordinate tables (FP64 and FP32)
+        p = j.problem
+        return 4 * p.points * self.elem + sum(p.n) * 3 * (8 + 4) + 4096
+
+    def _engine(self, key):
+        if key not in self.engines:
+            self.engines[key] = self.hj.Batch(*self.cfg)
+            self.streams[key] = self.torch.cuda.Stream(device=self.device)
+        return self.engines[key], self.streams[key]
+
+    def admit(self, j: Job):
+        torch = self.torch
+        p = j.problem
+        _, stream = self._engine(j.key)
+        v0h = self.v0_cache.get(j.rid)
+        if v0h is None:
+            v0h = p.v0()
+        try:
+            with torch.cuda.stream(stream):
+                v0 = torch.from_numpy(np.ascontiguousarray(v0h)).to(self.device, self.dtype,
+                                                                     non_blocking=False)
+                v = v0.clone()
+                a = torch.empty_like(v0)
+                b = torch.empty_like(v0)
+        except RuntimeError as e:  # torch reports device OOM as RuntimeError
+            raise MemoryError(str(e))
+        g = self.hj.Grid.from_problem(p, self.prec)
+        g.set_workspace(a, b)
+        j.dev = {"grid": g, "v0": v0, "v": v}
+        j.t = p.t0
+        j.dev_finished = p.tf <= p.t0
+
+    def advance(self, key, group: List[Job], max_steps: int):
+        eng, stream = self._engine(key)
+        todo = [j for j in group if not j.dev_finished]
+        if not todo:
+            return
+        ts, taken, fin = eng.step([j.dev["grid"] for j in todo], [j.dev["v0"] for j in todo],
+                                  [j.dev["v"] for j in todo], [j.problem.t0 for j in todo],
+                                  [j.t for j in todo], [j.problem.tf for j in todo],
+                                  [j.problem.mode for j in todo], max_steps, stream)
+        for j, t, k, f in zip(todo, ts, taken, fin):
+            j.t = t
+            j.steps_done += k
+            j.dev_finished = f
+
+    def sync(self, key):
+        eng, stream = self._engine(key)
+        stream.synchronize()
+
+    def idle(self, key):
+        pass
+
+    def result(self, j: Job) -> np.ndarray:
+        return j.dev["v"].double().cpu().numpy()
+
+    def release(self, j: Job):
+        j.dev["grid"].close()
+        j.dev = None
+
+    def close(self):
+        for e in self.engines.values():
+            e.close()
+        self.engines.clear()
+
+
+def run_plain(requests: Sequence[inputs.Request], prec: str = "fp32",
+              v0_cache: Optional[Dict[int, np.ndarray]] = None, keep_results: bool = False,
+              clock=time.perf_counter, sleep=time.sleep) -> Tuple[ServeReport, List[Job]]:
+    """The same requests one at a time through hj_solve (no batching, no
+    graph): each starts when it has arrived and the previous one finished."""
+    import torch
+
+    from . import hj
+
+    dtype = torch.float32 if prec == "fp32" else torch.float64
+    jobs = [Job(k, r.problem, r.arrival, t=r.problem.t0) for k, r in enumerate(requests)]
+    order = sorted(jobs, key=lambda j: (j.arrival, j.rid))
+    stream = torch.cuda.current_stream()
+    updates = 0.0
+    start = clock()
+    for j in order:
+        wait = j.arrival - (clock() - start)
+        while wait > 0:
+            sleep(min(wait, 0.05))
+            wait = j.arrival - (clock() - start)
+        p = j.problem
+        v0h = (v0_cache or {}).get(j.rid)
+        v0 = torch.from_numpy(np.ascontiguousarray(v0h if v0h is not None else p.v0())).to(
+            "cuda", dtype)
+        out = torch.empty_like(v0)
+        g = hj.Grid.from_problem(p, prec)
+        _, _, steps = g.schedule(p.t0, p.tf, stream)
+        g.solve(v0, out, p.t0, p.tf, p.mode, stream)
+        stream.synchronize()
+        if keep_results:
+            j.result = out.double().cpu().numpy()
+        g.close()
+        j.state = "done"
+        j.steps_done = steps
+        j.finished_at = clock() - start
+        updates += float(p.points) * steps
+    makespan = clock() - start
+    return report(jobs, makespan, 1, 0, len(jobs), updates), jobs

@@ -1,0 +1,127 @@
+"""Serving loop scheduling on the CPU with a fake device backend: admission
+by bytes and slots, continuous joining, rejection and failure paths, latency
+and throughput accounting."""
+import math
+
+import pytest
+
+from paper_2507_11542_amd import inputs
+from paper_2507_11542_amd.serve import Server
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, s):
+        self.t += s
+
+
+class FakeBackend:
+    """Each macro-iteration costs 1 ms of fake time; a request needs
+    ceil(tf / 0.1) steps."""
+
+    def __init__(self, clock, fail_names=()):
+        self.clock = clock
+        self.fail_names = set(fail_names)
+        self.live = 0
+        self.max_live = 0
+        self.released = []
+
+    def bytes_needed(self, j):
+        return j.problem.points * 16
+
+    def admit(self, j):
+        if j.problem.name in self.fail_names:
+            raise MemoryError("injected")
+        j.dev = {"left": int(math.ceil(j.problem.tf / 0.1))}
+        j.dev_finished = j.dev["left"] == 0
+        self.live += 1
+        self.max_live = max(self.max_live, self.live)
+
+    def advance(self, key, group, k):
+        for j in group:
+            n = min(k, j.dev["left"])
+            j.dev["left"] -= n
+            j.steps_done += n
+            j.dev_finished = j.dev["left"] == 0
+
+    def sync(self, key):
+        self.clock.t += 0.001
+
+    def idle(self, key):
+        pass
+
+    def result(self, j):
+        return None
+
+    def release(self, j):
+        self.live -= 1
+        self.released.append(j.rid)
+
+
+def _req(arrival, n, tf, name="p", dyn="rel_dubins"):
+    p = inputs.rel_dubins_3d(n=(n, n, n), tf=tf).with_(name=name)
+    return inputs.Request(arrival, p)
+
+
+def test_all_complete_and_account():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    reqs = [_req(0.0005 * k, 11, 0.35 + 0.1 * (k % 3)) for k in range(12)]
+    rep, jobs = Server(be, hbm_budget=10 ** 9, macro_steps=2, clock=clk, sleep=clk.sleep).run(reqs)
+    assert rep.completed == 12 and rep.rejected == 0
+    assert all(j.state == "done" and j.latency > 0 for j in jobs)
+    steps = sum(math.ceil(r.problem.tf / 0.1) for r in reqs)
+    assert rep.updates == pytest.approx(11 ** 3 * steps)
+    assert be.live == 0 and sorted(be.released) == list(range(12))
+    assert rep.p99_s >= rep.p50_s > 0
+
+
+def test_budget_limits_concurrency_and_late_requests_join():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    per = 11 ** 3 * 16
+    reqs = [_req(0.0, 11, 1.0) for _ in range(3)] + [_req(0.0025, 11, 0.2)]
+    rep, jobs = Server(be, hbm_budget=2 * per, macro_steps=1, clock=clk, sleep=clk.sleep).run(reqs)
+    assert rep.completed == 4
+    assert be.max_live == 2 and rep.max_active == 2 and rep.peak_bytes == 2 * per
+    # the third request waits for memory, then joins while another still runs
+    first_done = min(j.finished_at for j in jobs[:2])
+    assert jobs[2].admitted_at >= first_done
+    assert any(j.finished_at > jobs[2].admitted_at for j in jobs[:2] if j.rid != 2) or \
+        jobs[3].admitted_at < jobs[2].finished_at
+
+
+def test_slot_limit():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    reqs = [_req(0.0, 11, 0.3) for _ in range(5)]
+    rep, _ = Server(be, hbm_budget=10 ** 9, max_active=2, macro_steps=1, clock=clk,
+                    sleep=clk.sleep).run(reqs)
+    assert rep.completed == 5 and be.max_live == 2
+
+
+def test_over_budget_and_failed_allocation_are_rejected():
+    clk = FakeClock()
+    be = FakeBackend(clk, fail_names={"boom"})
+    reqs = [_req(0.0, 11, 0.3), _req(0.0, 41, 0.3, name="huge"), _req(0.0, 11, 0.3, name="boom"),
+            _req(0.001, 11, 0.2)]
+    rep, jobs = Server(be, hbm_budget=2 * 11 ** 3 * 16, macro_steps=1, clock=clk,
+                       sleep=clk.sleep).run(reqs)
+    assert rep.rejected == 2 and rep.completed == 2
+    assert "budget" in jobs[1].reason and "allocation failed" in jobs[2].reason
+    assert be.live == 0
+
+
+def test_idle_waits_for_arrivals():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    reqs = [_req(0.5, 11, 0.2), _req(1.25, 11, 0.2)]
+    rep, jobs = Server(be, hbm_budget=10 ** 9, macro_steps=4, clock=clk, sleep=clk.sleep).run(reqs)
+    assert rep.completed == 2
+    assert jobs[0].admitted_at >= 0.5 and jobs[1].admitted_at >= 1.25
+    assert rep.makespan_s >= 1.25
