@@ -101,6 +101,99 @@ def cpu_baseline(p, target_s: float = 15.0):
                       "(FP64 C oracle, OpenMP over nodes), %.1f s" % (nsteps, k, el)}
 
 
+def bench_batched(args):
+    """64 relative-Dubins tubes of uneven size (N ~ U{51,61,81,101}, seeded
+    speeds and turn bounds), FP32 with FP64 time: one batched solve (round
+    launches replayed from a captured graph, autotuned tile shape) against the
+    same instances one at a time through hj_solve."""
+    import numpy as np
+    import torch
+
+    from paper_2507_11542_amd import autotune, hj, inputs
+
+    prec = "fp32"
+    probs = inputs.rel_dubins_batch(args.batch_count, seed=0)
+    stream = torch.cuda.current_stream()
+    grids = [hj.Grid.from_problem(p, prec) for p in probs]
+    v0s = [torch.from_numpy(p.v0()).to("cuda", torch.float32) for p in probs]
+    outs = [torch.empty_like(v) for v in v0s]
+    steps = [g.schedule(p.t0, p.tf, stream)[2] for g, p in zip(grids, probs)]
+    updates = float(sum(p.points * k for p, k in zip(probs, steps)))
+    (tile, wg), timings = autotune.tune(probs, grids, v0s, prec, stream=stream)
+    b = hj.Batch(tile_nodes=tile, workgroups=wg, use_graph=True)
+    t0s = [p.t0 for p in probs]
+    tfs = [p.tf for p in probs]
+    modes = [p.mode for p in probs]
+    b.solve(grids, v0s, outs, t0s, tfs, modes, stream)  # warm-up (capture)
+    b.wait(len(probs), stream)
+    t = time.perf_counter()
+    b.solve(grids, v0s, outs, t0s, tfs, modes, stream)
+    tfin, items = b.wait(len(probs), stream)
+    batched_s = time.perf_counter() - t
+    # plain: the same instances one at a time
+    plain_out = [torch.empty_like(v) for v in v0s]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for g, p, v, o in zip(grids, probs, v0s, plain_out):
+        g.solve(v, o, p.t0, p.tf, p.mode, stream)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t
+    same = all(torch.equal(a, c) for a, c in zip(outs, plain_out))
+    b.close()
+    for g in grids:
+        g.close()
+    return {"workload": "%d relative-Dubins tubes, N~U{51,61,81,101}, ve,vp~U[3,6], "
+                        "we,wp~U[0.5,1.5] (rng 0), WENO5+LF+RK3, t=2.8" % len(probs),
+            "dtype": "f32 (FP64 t, dt, alpha)", "points": int(sum(p.points for p in probs)),
+            "rk_steps_total": int(sum(steps)), "updates": updates,
+            "batched_s": batched_s, "batched_updates_per_s": updates / batched_s,
+            "plain_s": plain_s, "plain_updates_per_s": updates / plain_s,
+            "speedup_vs_plain": plain_s / batched_s, "tile_nodes": tile, "workgroups": wg,
+            "autotune_ms_per_step": timings, "batched_equals_plain_bitwise": bool(same),
+            "t_final_max_err": float(max(abs(a - p.tf) for a, p in zip(tfin, probs)))}
+
+
+def bench_served(args):
+    """Poisson stream of double-integrator (101^2..401^2), relative-Dubins
+    (51^3..121^3) and 4-D Dubins (41^4..61^4) requests, WENO5+LF+RK3, FP32,
+    horizons U[0.5,3]: served with continuous batching at several arrival
+    rates (relative to the saturated completion rate) against the same
+    requests one at a time through hj_solve."""
+    import numpy as np
+
+    from paper_2507_11542_amd import inputs
+    from paper_2507_11542_amd.serve import GpuBackend, Server, run_plain
+
+    n = args.serve_requests
+    base = inputs.serving_stream(count=n, rate=1.0, seed=0)
+    v0_cache = {k: r.problem.v0().astype(np.float32) for k, r in enumerate(base)}
+
+    def at_rate(rate):
+        return [inputs.Request(r.arrival / rate, r.problem) for r in base]
+
+    def served(rate):
+        print("[bench] served at %.3g req/s" % rate, file=sys.stderr, flush=True)
+        be = GpuBackend(prec="fp32", v0_cache=v0_cache)
+        try:
+            rep, _ = Server(be, hbm_budget=int(args.serve_budget_gib * (1 << 30)),
+                            macro_steps=args.macro_steps).run(at_rate(rate))
+        finally:
+            be.close()
+        return rep.as_dict()
+
+    sat = served(1e9)  # everything arrives at once: saturated throughput
+    lam_sat = sat["completed"] / sat["makespan_s"]
+    runs = {"saturated": sat}
+    for f in args.serve_rates:
+        runs["%.2fx" % f] = dict(served(f * lam_sat), rate_req_per_s=f * lam_sat)
+    plain_rep, _ = run_plain(at_rate(1e9), prec="fp32", v0_cache=v0_cache)
+    plain = plain_rep.as_dict()
+    return {"workload": "%d requests, thirds DI 101^2..401^2 / rel-Dubins 51^3..121^3 / "
+                        "4-D Dubins 41^4..61^4, WENO5+LF+RK3, FP32, Poisson (seed 0)" % n,
+            "saturated_rate_req_per_s": lam_sat, "served": runs, "plain_all_at_once": plain,
+            "served_vs_plain_updates_per_s": sat["updates_per_s"] / plain["updates_per_s"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +203,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=40,
                     help="RK steps timed with HIP events for the kernel roofline")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=96)
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.5, 0.9])
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--macro-steps", type=int, default=32)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates "
                          "the HBM byte counters of a profiler run)")
@@ -207,7 +307,14 @@ def main() -> int:
                      "flops_per_node_stage": weno5_flops_per_node_stage(p.ndim)},
         "error_vs_oracle_fp64": err,
     }
+    if not args.no_batch:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        rec["batched"] = bench_batched(args)
+    if not args.no_serve:
+        print("[bench] served leg", file=sys.stderr, flush=True)
+        rec["served"] = bench_served(args)
     if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(rec))
     return 0
