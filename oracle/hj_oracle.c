@@ -157,42 +157,79 @@ static double line_value(const ogrid *g, const double *v, long node, int d, long
 
 /* ------------------------------------------------- one-sided derivatives */
 
-/* Sec. 3.3, Jiang-Peng WENO5 from five consecutive one-sided differences
- * (Osher-Fedkiw eqs. 3.28-3.39); reading R3 for eps.  The constant fractions
- * are multiplied as precomputed doubles and the three weights are normalised
- * by one division of the weighted sum: the same formulas, written so that a
- * device implementation can reproduce every rounding. */
+/* Sec. 3.3, Jiang-Peng WENO5 (Osher-Fedkiw eqs. 3.28-3.39), reading R3 for
+ * eps.  The left-biased approximation at node i uses the five consecutive
+ * differences D1 at i-5/2 .. i+3/2; the right-biased one at node i-1 uses the
+ * same five differences in reverse order.  Both are written here on the
+ * window w0..w4 (increasing grid order):
+ *   smoothness on the three triples, with e = (a + c) - 2b:
+ *     SA = 13/12 e^2 + 1/4 ((a + 3c) - 4b)^2   on (w0, w1, w2)
+ *     SB = 13/12 e^2 + 1/4 (a - c)^2           on (w1, w2, w3)
+ *     SC = 13/12 e^2 + 1/4 ((3a + c) - 4b)^2   on (w2, w3, w4)
+ *   (the left-biased S1, S2, S3 are SA, SB, SC; the right-biased S1, S2, S3
+ *   are SC, SB, SA: the same values),
+ *   eps = 1e-6 max_k w_k^2 + 1e-99, r_X = 1/(S_X + eps)^2,
+ *   weights gamma = (0.1, 0.6, 0.3) on (rA, rB, rC) for the left-biased and on
+ *   (rC, rB, rA) for the right-biased approximation, normalised by one
+ *   division of the weighted sum of the third-order candidates.
+ * The constant fractions are multiplied as precomputed doubles.  Every
+ * quantity shared by the two approximations of a window is rounded the same
+ * way in both, so a device implementation may evaluate it once. */
 static const double C1_3 = 1.0 / 3.0, C1_6 = 1.0 / 6.0, C5_6 = 5.0 / 6.0,
                     C7_6 = 7.0 / 6.0, C11_6 = 11.0 / 6.0, C13_12 = 13.0 / 12.0;
 
-static double weno5(double v1, double v2, double v3, double v4, double v5)
+typedef struct {
+    double ra, rb, rc; /* reciprocal squared regularised smoothness */
+} wweights;
+
+static wweights weno_window(const double *w)
 {
-    /* third-order candidates on the three substencils */
+    double ea = (w[0] + w[2]) - 2.0 * w[1];
+    double eb = (w[1] + w[3]) - 2.0 * w[2];
+    double ec = (w[2] + w[4]) - 2.0 * w[3];
+    double fa = (w[0] + 3.0 * w[2]) - 4.0 * w[1];
+    double fb = w[1] - w[3];
+    double fc = (3.0 * w[2] + w[4]) - 4.0 * w[3];
+    double sa = C13_12 * ea * ea + 0.25 * fa * fa;
+    double sb = C13_12 * eb * eb + 0.25 * fb * fb;
+    double sc = C13_12 * ec * ec + 0.25 * fc * fc;
+
+    double mx = w[0] * w[0];
+    for (int k = 1; k < 5; ++k)
+        if (w[k] * w[k] > mx) mx = w[k] * w[k];
+    double eps = 1e-6 * mx + 1e-99;
+
+    wweights r;
+    r.ra = 1.0 / ((sa + eps) * (sa + eps));
+    r.rb = 1.0 / ((sb + eps) * (sb + eps));
+    r.rc = 1.0 / ((sc + eps) * (sc + eps));
+    return r;
+}
+
+/* WENO5 blend of the candidates on v1..v5 with the reciprocal weights
+ * r1, r2, r3 of their substencils */
+static double weno_blend(double v1, double v2, double v3, double v4, double v5,
+                         double r1, double r2, double r3)
+{
     double phi1 = v1 * C1_3 - v2 * C7_6 + v3 * C11_6;
     double phi2 = -v2 * C1_6 + v3 * C5_6 + v4 * C1_3;
     double phi3 = v3 * C1_3 + v4 * C5_6 - v5 * C1_6;
-
-    /* smoothness indicators */
-    double e1 = v1 - 2.0 * v2 + v3, f1 = v1 - 4.0 * v2 + 3.0 * v3;
-    double e2 = v2 - 2.0 * v3 + v4, f2 = v2 - v4;
-    double e3 = v3 - 2.0 * v4 + v5, f3 = 3.0 * v3 - 4.0 * v4 + v5;
-    double s1 = C13_12 * e1 * e1 + 0.25 * f1 * f1;
-    double s2 = C13_12 * e2 * e2 + 0.25 * f2 * f2;
-    double s3 = C13_12 * e3 * e3 + 0.25 * f3 * f3;
-
-    double mx = v1 * v1;
-    if (v2 * v2 > mx) mx = v2 * v2;
-    if (v3 * v3 > mx) mx = v3 * v3;
-    if (v4 * v4 > mx) mx = v4 * v4;
-    if (v5 * v5 > mx) mx = v5 * v5;
-    double eps = 1e-6 * mx + 1e-99;
-
-    /* weights alpha_k = gamma_k / (S_k + eps)^2, gamma = (0.1, 0.6, 0.3);
-     * result sum_k alpha_k phi_k / sum_k alpha_k */
-    double a1 = 0.1 / ((s1 + eps) * (s1 + eps));
-    double a2 = 0.6 / ((s2 + eps) * (s2 + eps));
-    double a3 = 0.3 / ((s3 + eps) * (s3 + eps));
+    double a1 = 0.1 * r1, a2 = 0.6 * r2, a3 = 0.3 * r3;
     return (a1 * phi1 + a2 * phi2 + a3 * phi3) / (a1 + a2 + a3);
+}
+
+/* left-biased approximation (p- of the node right of the window centre) */
+static double weno_left(const double *w)
+{
+    wweights r = weno_window(w);
+    return weno_blend(w[0], w[1], w[2], w[3], w[4], r.ra, r.rb, r.rc);
+}
+
+/* right-biased approximation (p+ of the node left of the window centre) */
+static double weno_right(const double *w)
+{
+    wweights r = weno_window(w);
+    return weno_blend(w[4], w[3], w[2], w[1], w[0], r.rc, r.rb, r.ra);
 }
 
 /* ENO choice of the smaller second difference, tie to the first argument
@@ -239,9 +276,9 @@ static void derivs_at(const ogrid *g, const double *v, long node, int d,
     double d1[6];
     for (int k = 0; k < 6; ++k) d1[k] = (s[k + 1] - s[k]) * inv_dx;
     /* p-: D-v at i-2..i+2 = D1 at i-5/2..i+3/2 */
-    *pm = weno5(d1[0], d1[1], d1[2], d1[3], d1[4]);
-    /* p+: D+v at i+2..i-2 = D1 at i+5/2..i-3/2 */
-    *pp = weno5(d1[5], d1[4], d1[3], d1[2], d1[1]);
+    *pm = weno_left(&d1[0]);
+    /* p+: D+v at i+2..i-2 = D1 at i+5/2..i-3/2, the window d1[1..5] reversed */
+    *pp = weno_right(&d1[1]);
 }
 
 /* ------------------------------------------------------------ dynamics */
@@ -356,17 +393,19 @@ static double cfl_dt(const ogrid *g, const double *alpha, double cfl)
 
 /* Sec. 4, Lax-Friedrichs:
  *   Hhat = H(x, (p+ + p-)/2) - sum_d alpha_d (p+_d - p-_d)/2,
- * and the semi-discrete right-hand side L(V) = -Hhat (from V_t + H = 0). */
+ * (the dissipation summed over the axes in order, then subtracted) and the
+ * semi-discrete right-hand side L(V) = -Hhat (from V_t + H = 0). */
 static double rhs_at(const ogrid *g, const odyn *dy, int scheme,
                      const double *alpha, const double *v, long node)
 {
     double pm[ORC_MAXD], pp[ORC_MAXD], pbar[ORC_MAXD];
+    double diss = 0.0;
     for (int d = 0; d < g->nd; ++d) {
         derivs_at(g, v, node, d, scheme, &pm[d], &pp[d]);
         pbar[d] = (pp[d] + pm[d]) / 2.0;
+        diss += alpha[d] * ((pp[d] - pm[d]) / 2.0);
     }
-    double hhat = hamiltonian(g, dy, node, pbar);
-    for (int d = 0; d < g->nd; ++d) hhat -= alpha[d] * ((pp[d] - pm[d]) / 2.0);
+    double hhat = hamiltonian(g, dy, node, pbar) - diss;
     return -hhat;
 }
 

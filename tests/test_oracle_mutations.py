@@ -21,12 +21,14 @@ MUTATIONS = {
     "eno2_picks_larger": ("return fabs(a) <= fabs(b) ? a : b;", "return fabs(a) <= fabs(b) ? b : a;"),
     "eno2_second_difference_scale": ("(d1[k + 1] - d1[k]) * g->inv_2dx[d]",
                                      "(d1[k + 1] - d1[k]) * inv_dx"),
-    "weno_linear_weights_swapped": ("double a1 = 0.1 /", "double a1 = 0.3 /"),
+    "weno_linear_weights_swapped": ("double a1 = 0.1 * r1, a2 = 0.6 * r2, a3 = 0.3 * r3;",
+                                    "double a1 = 0.3 * r1, a2 = 0.6 * r2, a3 = 0.1 * r3;"),
     "weno_candidate_coefficient": ("v3 * C11_6", "v3 * C5_6"),
-    "weno_smoothness_term": ("f2 = v2 - v4;", "f2 = v2 + v4;"),
-    "weno_right_stencil_order": ("weno5(d1[5], d1[4], d1[3], d1[2], d1[1])",
-                                 "weno5(d1[1], d1[2], d1[3], d1[4], d1[5])"),
-    "lf_dissipation_sign": ("hhat -= alpha[d] *", "hhat += alpha[d] *"),
+    "weno_smoothness_term": ("double fb = w[1] - w[3];", "double fb = w[1] + w[3];"),
+    "weno_right_weights_order": ("w[4], w[3], w[2], w[1], w[0], r.rc, r.rb, r.ra",
+                                 "w[4], w[3], w[2], w[1], w[0], r.ra, r.rb, r.rc"),
+    "weno_right_stencil_order": ("*pp = weno_right(&d1[1]);", "*pp = weno_left(&d1[1]);"),
+    "lf_dissipation_sign": ("diss += alpha[d] *", "diss -= alpha[d] *"),
     "rhs_sign": ("    return -hhat;\n}", "    return hhat;\n}"),
     "rk2_combination": ("v[k] = (v[k] + v2) / 2.0;", "v[k] = v2;"),
     "rk3_middle_stage": ("w2[k] = (3.0 * v[k] + v2) / 4.0;", "w2[k] = (v[k] + v2) / 2.0;"),
