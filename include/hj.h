@@ -107,6 +107,17 @@ hj_status hj_set_scheme(hj_grid_t g, hj_space space, hj_time time, double cfl);
 hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double tf,
                    hj_mode mode, void *hip_stream);
 
+/* Precision form of hj_solve for an HJ_FP32 grid: V0 and V_out are FP64
+ * device arrays; V0 is rounded to FP32, the whole solve runs in FP32 storage
+ * and arithmetic (alpha, dt and t in FP64), and the result is widened to FP64
+ * with the tube comparison of Sec. 6.1 taken again in FP64 where the zero
+ * level set lies: V_out = min(V32, V0) on the band |V32| <= band (HJ_TUBE),
+ * V32 elsewhere.  band < 0 selects 3 max(dx).  The handle keeps two FP32
+ * working arrays.  HJ_E_ARG on an FP64 grid or the argument errors of
+ * hj_solve. */
+hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0, double tf,
+                         hj_mode mode, double band, void *hip_stream);
+
 /* One full TVD-RK step in place on V (device), of size min(dt, tf - *t),
  * then the tube update against V0 when mode is HJ_TUBE (V0 may be NULL for
  * HJ_SET).  *t advances by the step (FP64, host); *dt_used receives it
@@ -141,8 +152,9 @@ typedef struct hj_batch_s *hj_batch_t;
 /* New batch engine on the current device. */
 hj_status hj_batch_create(hj_batch_t *out);
 
-/* Launch shape: tile_nodes nodes per tile (multiple of 256, in [256, 2^22];
- * default 4096), workgroups of 256 threads per round launch striding over the
+/* Launch shape: tile_nodes the largest tile (multiple of 256, in
+ * [256, 2^22]; default 4096; an instance's tiles shrink, in steps of 256, so
+ * that it has at least 512 of them when it can), workgroups of 256 threads per round launch striding over the
  * round's tiles (in [1, 65536]; default 1024), use_graph != 0 to replay a
  * captured hipGraph (default) instead of direct launches. */
 hj_status hj_batch_config(hj_batch_t b, int tile_nodes, int workgroups, int use_graph);

@@ -420,6 +420,36 @@ hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double t
     return run_steps<float>(g, V_out, V0, tube, hs, st);
 }
 
+hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0, double tf,
+                         hj_mode mode, double band, void *hip_stream)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (g->prec != HJ_FP32) return fail(HJ_E_ARG, "hj_solve_mixed needs an HJ_FP32 grid");
+    if (!V0 || !V_out) return fail(HJ_E_ARG, "V0 and V_out must be non-NULL");
+    if (mode != HJ_SET && mode != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
+    if (!(std::isfinite(t0) && std::isfinite(tf) && tf >= t0))
+        return fail(HJ_E_ARG, "need finite t0 <= tf");
+    const size_t b64 = size_t(g->total) * sizeof(double);
+    if (overlap(V0, V_out, b64)) return fail(HJ_E_ARG, "V_out overlaps V0");
+    if (band < 0.0) {
+        double m = 0.0;
+        for (int d = 0; d < g->nd; ++d) m = g->dx[d] > m ? g->dx[d] : m;
+        band = 3.0 * m;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = use_device(g)) != HJ_OK) return s;
+    if (!g->mixV && (s = dev_alloc(&g->mixV, g->bytes(), "mixed V")) != HJ_OK) return s;
+    if (!g->mixV0 && (s = dev_alloc(&g->mixV0, g->bytes(), "mixed V0")) != HJ_OK) return s;
+    hipError_t e = launch_round_to_f32(V0, (float *)g->mixV0, uint32_t(g->total), st);
+    if (e != hipSuccess) return hip_fail(e, "round to fp32");
+    if ((s = hj_solve(g, g->mixV0, g->mixV, t0, tf, mode, hip_stream)) != HJ_OK) return s;
+    e = launch_finalize_f64((const float *)g->mixV, V0, V_out, uint32_t(g->total), band,
+                            mode == HJ_TUBE ? 1 : 0, st);
+    if (e != hipSuccess) return hip_fail(e, "fp64 finalize");
+    return HJ_OK;
+}
+
 hj_status hj_step(hj_grid_t g, void *V, const void *V0, double *t, double tf, hj_mode mode,
                   double *dt_used, void *hip_stream)
 {
@@ -487,6 +517,8 @@ hj_status hj_grid_destroy(hj_grid_t g)
     if (g->tab32) (void)hipFree(g->tab32);
     if (g->own_bufs && g->bufA) (void)hipFree(g->bufA);
     if (g->own_bufs && g->bufB) (void)hipFree(g->bufB);
+    if (g->mixV) (void)hipFree(g->mixV);
+    if (g->mixV0) (void)hipFree(g->mixV0);
     if (g->partial) (void)hipFree(g->partial);
     if (g->alpha_dev) (void)hipFree(g->alpha_dev);
     if (g->alpha_host) (void)hipHostFree(g->alpha_host);

@@ -204,9 +204,20 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, uint3
     return HJ_OK;
 }
 
+// Nodes per tile of one instance: the configured maximum, shrunk (in steps
+// of 256) so that the instance has at least kMinTiles tiles when it can.
+constexpr uint32_t kMinTiles = 512;
+
+uint32_t instance_tile(uint32_t total, uint32_t max_tile)
+{
+    uint32_t t = (total + kMinTiles - 1) / kMinTiles;
+    t = (t + 255u) & ~255u;
+    return t < 256u ? 256u : (t > max_tile ? max_tile : t);
+}
+
 template <typename T>
 void fill_inst(void *dst, hj_grid_t g, void *vout, const void *v0, double dt, double t0,
-               double tf, uint32_t tiles, uint32_t steps, bool tube)
+               double tf, uint32_t tiles, uint32_t tile_nodes, uint32_t steps, bool tube)
 {
     BatchInst<T> in;
     std::memset(&in, 0, sizeof(in));
@@ -219,6 +230,7 @@ void fill_inst(void *dst, hj_grid_t g, void *vout, const void *v0, double dt, do
     in.t0 = t0;
     in.tf = tf;
     in.tiles = tiles;
+    in.tile_nodes = tile_nodes;
     in.steps = steps;
     in.tube = tube ? 1 : 0;
     std::memcpy(dst, &in, sizeof(in));
@@ -334,7 +346,7 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
     if (any) HJ_HIP(hipStreamSynchronize(st), "alpha synchronise");
 
     std::vector<double> dts(n);
-    std::vector<uint32_t> steps(n), tiles(n);
+    std::vector<uint32_t> steps(n), tiles(n), tsize(n);
     uint32_t max_n = 0;
     for (int i = 0; i < n; ++i) {
         if (!gs[i]->alpha_valid) accept_alpha(gs[i]);
@@ -350,7 +362,8 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
             }
         steps[i] = k;
         if (t_reached) t_reached[i] = t;
-        tiles[i] = uint32_t((gs[i]->total + b->tile_nodes - 1) / b->tile_nodes);
+        tsize[i] = instance_tile(uint32_t(gs[i]->total), b->tile_nodes);
+        tiles[i] = uint32_t((gs[i]->total + tsize[i] - 1) / tsize[i]);
         max_n = std::max(max_n, steps[i]);
     }
     const uint32_t order = uint32_t(g0->order);
@@ -385,11 +398,11 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
         const bool tube = modes[i] == HJ_TUBE;
         const void *v0 = V0s ? V0s[i] : nullptr;
         if (g0->prec == HJ_FP64)
-            fill_inst<double>(dst, gs[i], Vs[i], v0, dts[i], tcur[i], tf[i], tiles[i], steps[i],
-                              tube);
+            fill_inst<double>(dst, gs[i], Vs[i], v0, dts[i], tcur[i], tf[i], tiles[i], tsize[i],
+                              steps[i], tube);
         else
-            fill_inst<float>(dst, gs[i], Vs[i], v0, dts[i], tcur[i], tf[i], tiles[i], steps[i],
-                             tube);
+            fill_inst<float>(dst, gs[i], Vs[i], v0, dts[i], tcur[i], tf[i], tiles[i], tsize[i],
+                             steps[i], tube);
     }
     std::memset(b->h_gl, 0, sizeof(BatchGlobal));
     b->h_gl->items = uint32_t(total);

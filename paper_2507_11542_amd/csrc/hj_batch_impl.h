@@ -4,7 +4,8 @@
 // Round r is stage r % order of RK step r / order.  The instances are sorted
 // by step count (descending), so the instances still running in round r are
 // a prefix of that order; the round's work is the concatenation of their
-// tiles (tile_nodes nodes each).  The round kernel's workgroups stride over
+// tiles (each instance's own tile size: the configured maximum, shrunk so a
+// small instance still spreads over enough workgroups).  The round kernel's workgroups stride over
 // those tiles; the kernel boundary between rounds is the only barrier, so no
 // workgroup ever waits on another.  All rounds are launched back to back (and
 // captured once in a hipGraph by the host), each kernel reading the round
@@ -15,7 +16,7 @@
 // of the step's last stage stores t_n + h into the other slot.
 #pragma once
 
-#include "hj_stage_impl.h"
+#include "hj_launch_impl.h"
 
 namespace hj {
 
@@ -27,10 +28,10 @@ struct BatchInst {
     T *b;              // stage buffer B
     const T *v0;       // V0 (tube target)
     double dt, t0, tf; // CFL step and horizon (FP64)
-    uint32_t tiles;    // items per round
+    uint32_t tiles;    // tiles per round
     uint32_t steps;    // RK steps
+    uint32_t tile_nodes;  // nodes per tile of this instance
     int tube;
-    int pad;
 };
 
 struct BatchCtl {
@@ -80,6 +81,70 @@ __device__ inline uint32_t upper_index(const uint32_t *a, uint32_t n, uint32_t x
     return lo;
 }
 
+// Arguments of stage (r % order) of instance `inst` for round r, and the
+// step size h of that step (from the instance's device time t_n).
+template <typename T>
+__device__ inline StageArgs<T> batch_stage_args(const BatchPtrs<T> &p, uint32_t inst, uint32_t r,
+                                                double *h_out, double *tn_out)
+{
+    const uint32_t order = p.gl->order;
+    const uint32_t stage = r % order, step = r / order;
+    const BatchInst<T> &in = p.inst[inst];
+    const double t_n = p.ctl[inst].t[step & 1u];
+    const double rem = in.tf - t_n;
+    const double h = in.dt < rem ? in.dt : rem;
+    StageArgs<T> a = in.geo;
+    a.dt = T(h);
+    a.v0 = in.v0;
+    a.tube = 0;
+    if (stage == 0) {
+        a.vs = in.v;
+        a.vb = nullptr;
+        a.out = in.a;
+        a.combine = kEuler;
+    } else if (stage == 1 && order == 3) {
+        a.vs = in.a;
+        a.vb = in.v;
+        a.out = in.b;
+        a.combine = kBlend;
+        a.wb = T(3);
+        a.w2 = T(1);
+        a.den = T(4);
+    } else if (order == 2) {
+        a.vs = in.a;
+        a.vb = in.v;
+        a.out = in.v;
+        a.combine = kBlend;
+        a.wb = T(1);
+        a.w2 = T(1);
+        a.den = T(2);
+        a.tube = in.tube;
+    } else {
+        a.vs = in.b;
+        a.vb = in.v;
+        a.out = in.v;
+        a.combine = kBlend;
+        a.wb = T(1);
+        a.w2 = T(2);
+        a.den = T(3);
+        a.tube = in.tube;
+    }
+    *h_out = h;
+    *tn_out = t_n;
+    return a;
+}
+
+// the item k of round r: its instance and tile
+template <typename T>
+__device__ inline void batch_item(const BatchPtrs<T> &p, uint32_t begin, uint32_t k,
+                                  uint32_t *inst, uint32_t *tile)
+{
+    const uint32_t local = k - begin;
+    const uint32_t s = upper_index(p.tile_pre, p.gl->ninst, local);
+    *inst = __builtin_amdgcn_readfirstlane(p.sorted[s]);
+    *tile = __builtin_amdgcn_readfirstlane(local - p.tile_pre[s]);
+}
+
 template <typename T, int D, int SCH, int DYN>
 __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r)
 {
@@ -87,52 +152,12 @@ __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r)
     const uint32_t begin = p.round_off[r], end = p.round_off[r + 1];
     const uint32_t order = p.gl->order;
     const uint32_t stage = r % order, step = r / order;
-    const uint32_t tn = p.gl->tile_nodes;
     for (uint32_t k = begin + blockIdx.x; k < end; k += gridDim.x) {
-        const uint32_t local = k - begin;
-        const uint32_t s = upper_index(p.tile_pre, p.gl->ninst, local);
-        const uint32_t inst = __builtin_amdgcn_readfirstlane(p.sorted[s]);
-        const uint32_t tile = __builtin_amdgcn_readfirstlane(local - p.tile_pre[s]);
-        const BatchInst<T> &in = p.inst[inst];
-        const double t_n = p.ctl[inst].t[step & 1u];
-        const double rem = in.tf - t_n;
-        const double h = in.dt < rem ? in.dt : rem;
-        StageArgs<T> a = in.geo;
-        a.dt = T(h);
-        a.v0 = in.v0;
-        a.tube = 0;
-        if (stage == 0) {
-            a.vs = in.v;
-            a.vb = nullptr;
-            a.out = in.a;
-            a.combine = kEuler;
-        } else if (stage == 1 && order == 3) {
-            a.vs = in.a;
-            a.vb = in.v;
-            a.out = in.b;
-            a.combine = kBlend;
-            a.wb = T(3);
-            a.w2 = T(1);
-            a.den = T(4);
-        } else if (order == 2) {
-            a.vs = in.a;
-            a.vb = in.v;
-            a.out = in.v;
-            a.combine = kBlend;
-            a.wb = T(1);
-            a.w2 = T(1);
-            a.den = T(2);
-            a.tube = in.tube;
-        } else {
-            a.vs = in.b;
-            a.vb = in.v;
-            a.out = in.v;
-            a.combine = kBlend;
-            a.wb = T(1);
-            a.w2 = T(2);
-            a.den = T(3);
-            a.tube = in.tube;
-        }
+        uint32_t inst, tile;
+        batch_item(p, begin, k, &inst, &tile);
+        double h, t_n;
+        const StageArgs<T> a = batch_stage_args(p, inst, r, &h, &t_n);
+        const uint32_t tn = p.inst[inst].tile_nodes;
         const uint32_t first = tile * tn;
         const uint32_t last = first + tn < a.total ? first + tn : a.total;
         for (uint32_t node = first + threadIdx.x; node < last; node += 256)

@@ -35,6 +35,8 @@ struct hj_grid_s {
     void *bufA = nullptr;      // stage buffers
     void *bufB = nullptr;
     bool own_bufs = true;      // false after hj_grid_set_workspace
+    void *mixV = nullptr;      // hj_solve_mixed: FP32 V0 and V
+    void *mixV0 = nullptr;
     double *partial = nullptr; // alpha pass-1 partial maxima
     double *alpha_dev = nullptr;
     double *alpha_host = nullptr;  // pinned

@@ -60,4 +60,8 @@ uint32_t alpha_blocks(uint32_t total);
 hipError_t launch_alpha(int ndim, int dyn, const AlphaArgs &a, double *partial, double *alpha,
                         hipStream_t s);
 
+hipError_t launch_round_to_f32(const double *src, float *dst, uint32_t n, hipStream_t s);
+hipError_t launch_finalize_f64(const float *v32, const double *v0, double *out, uint32_t n,
+                               double band, int tube, hipStream_t s);
+
 }  // namespace hj

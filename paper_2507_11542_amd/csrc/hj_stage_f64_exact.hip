@@ -4,7 +4,7 @@
 // result is the rounding of a plain FP64 evaluation of the same formulas, so
 // ENO2's choice between two second differences and WENO5's weights see the
 // same values as such an evaluation, step after step.
-#include "hj_stage_impl.h"
+#include "hj_launch_impl.h"
 
 namespace hj {
 hipError_t launch_stage_f64(int ndim, int space, int dyn, const StageArgs<double> &a,

@@ -24,56 +24,83 @@ struct Halo<kEno2> { static constexpr int w = 2; };
 template <>
 struct Halo<kWeno5> { static constexpr int w = 3; };
 
-// Jiang-Peng WENO5 approximation from five consecutive one-sided differences
-// (Sec. 3.3; Osher-Fedkiw eqs. 3.28-3.39), eps = 1e-6 max v_k^2 + floor.
+// Jiang-Peng WENO5 (Sec. 3.3; Osher-Fedkiw eqs. 3.28-3.39) on a window of
+// five consecutive one-sided differences w0..w4 (increasing grid order).  The
+// left-biased approximation of the node right of the window centre and the
+// right-biased one of the node left of it share the window's smoothness
+// indicators, eps and reciprocal weights:
+//   SA = 13/12 e^2 + 1/4 ((a + 3c) - 4b)^2 on (w0,w1,w2), e = (a + c) - 2b
+//   SB = 13/12 e^2 + 1/4 (a - c)^2          on (w1,w2,w3)
+//   SC = 13/12 e^2 + 1/4 ((3a + c) - 4b)^2  on (w2,w3,w4)
+//   eps = 1e-6 max w_k^2 + floor, r_X = 1/(S_X + eps)^2
+// left-biased: gamma (0.1, 0.6, 0.3) on (rA, rB, rC); right-biased: on
+// (rC, rB, rA) with the window reversed.
 //
-// FP64: candidates, smoothness indicators and weights in the written order
-// with correctly rounded divisions, built without contraction, so every
-// rounding equals that of a plain FP64 evaluation of the same formulas.  The
-// discrete scheme amplifies rounding differences by up to ~1e11 over a long
-// horizon near the ridges of a game's value function, so FP64 results are only
-// comparable at 1e-12 when the rounding is reproduced.
-// FP32: fused multiply-adds and hardware reciprocals (v_rcp_f32); the floor
-// is 1e-18 because 1e-99 underflows in float.
+// FP64: every operation in the written order with correctly rounded
+// divisions, built without contraction, so each rounding equals that of a
+// plain FP64 evaluation of the same formulas (the scheme amplifies rounding
+// differences by up to ~1e11 over a long horizon near the ridges of a game's
+// value function, so FP64 results are only comparable at 1e-12 when the
+// rounding is reproduced).  FP32: fused multiply-adds and hardware
+// reciprocals (v_rcp_f32); the eps floor is 1e-18 because 1e-99 underflows.
 template <typename T>
-__device__ inline T weno5(T v1, T v2, T v3, T v4, T v5)
+struct WenoR {
+    T ra, rb, rc;
+};
+
+template <typename T>
+__device__ inline T wrecip(T x)
+{
+    if constexpr (sizeof(T) == 8)
+        return T(1) / x;
+    else
+        return __builtin_amdgcn_rcpf(x);
+}
+
+template <typename T>
+__device__ inline WenoR<T> weno_window(T w0, T w1, T w2, T w3, T w4)
 {
     constexpr T c13_12 = T(13.0 / 12.0);
+    const T ea = (w0 + w2) - T(2) * w1;
+    const T eb = (w1 + w3) - T(2) * w2;
+    const T ec = (w2 + w4) - T(2) * w3;
+    const T fa = (w0 + T(3) * w2) - T(4) * w1;
+    const T fb = w1 - w3;
+    const T fc = (T(3) * w2 + w4) - T(4) * w3;
+    const T sa = c13_12 * ea * ea + T(0.25) * fa * fa;
+    const T sb = c13_12 * eb * eb + T(0.25) * fb * fb;
+    const T sc = c13_12 * ec * ec + T(0.25) * fc * fc;
+    T mx = w0 * w0;
+    mx = fmax(mx, w1 * w1);
+    mx = fmax(mx, w2 * w2);
+    mx = fmax(mx, w3 * w3);
+    mx = fmax(mx, w4 * w4);
+    const T eps = T(1e-6) * mx + (sizeof(T) == 8 ? T(1e-99) : T(1e-18));
+    WenoR<T> r;
+    r.ra = wrecip((sa + eps) * (sa + eps));
+    r.rb = wrecip((sb + eps) * (sb + eps));
+    r.rc = wrecip((sc + eps) * (sc + eps));
+    return r;
+}
+
+// weighted blend of the third-order candidates on v1..v5 with the reciprocal
+// weights r1, r2, r3 of their substencils
+template <typename T>
+__device__ inline T weno_blend(T v1, T v2, T v3, T v4, T v5, T r1, T r2, T r3)
+{
     constexpr T c1_3 = T(1.0 / 3.0);
     constexpr T c1_6 = T(1.0 / 6.0);
     constexpr T c5_6 = T(5.0 / 6.0);
     constexpr T c7_6 = T(7.0 / 6.0);
     constexpr T c11_6 = T(11.0 / 6.0);
-
     const T phi1 = v1 * c1_3 - v2 * c7_6 + v3 * c11_6;
     const T phi2 = -v2 * c1_6 + v3 * c5_6 + v4 * c1_3;
     const T phi3 = v3 * c1_3 + v4 * c5_6 - v5 * c1_6;
-
-    const T e1 = v1 - T(2) * v2 + v3, f1 = v1 - T(4) * v2 + T(3) * v3;
-    const T e2 = v2 - T(2) * v3 + v4, f2 = v2 - v4;
-    const T e3 = v3 - T(2) * v4 + v5, f3 = T(3) * v3 - T(4) * v4 + v5;
-    const T s1 = c13_12 * e1 * e1 + T(0.25) * f1 * f1;
-    const T s2 = c13_12 * e2 * e2 + T(0.25) * f2 * f2;
-    const T s3 = c13_12 * e3 * e3 + T(0.25) * f3 * f3;
-
-    T mx = v1 * v1;
-    mx = fmax(mx, v2 * v2);
-    mx = fmax(mx, v3 * v3);
-    mx = fmax(mx, v4 * v4);
-    mx = fmax(mx, v5 * v5);
-    if constexpr (sizeof(T) == 8) {
-        const T eps = T(1e-6) * mx + T(1e-99);
-        const T a1 = T(0.1) / ((s1 + eps) * (s1 + eps));
-        const T a2 = T(0.6) / ((s2 + eps) * (s2 + eps));
-        const T a3 = T(0.3) / ((s3 + eps) * (s3 + eps));
+    const T a1 = T(0.1) * r1, a2 = T(0.6) * r2, a3 = T(0.3) * r3;
+    if constexpr (sizeof(T) == 8)
         return (a1 * phi1 + a2 * phi2 + a3 * phi3) / (a1 + a2 + a3);
-    } else {
-        const T eps = T(1e-6) * mx + T(1e-18);
-        const T a1 = T(0.1) * __builtin_amdgcn_rcpf((s1 + eps) * (s1 + eps));
-        const T a2 = T(0.6) * __builtin_amdgcn_rcpf((s2 + eps) * (s2 + eps));
-        const T a3 = T(0.3) * __builtin_amdgcn_rcpf((s3 + eps) * (s3 + eps));
-        return (a1 * phi1 + a2 * phi2 + a3 * phi3) * __builtin_amdgcn_rcpf(a1 + a2 + a3);
-    }
+    else
+        return (a1 * phi1 + a2 * phi2 + a3 * phi3) * wrecip(a1 + a2 + a3);
 }
 
 // ENO2 choice of the smaller second difference; ties go to the first (<=).
@@ -140,8 +167,11 @@ __device__ inline void axis_derivs(const T *__restrict__ v, uint32_t node, int i
         T d1[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) d1[k] = (s[k + 1] - s[k]) * inv_dx;
-        pm = weno5(d1[0], d1[1], d1[2], d1[3], d1[4]);
-        pp = weno5(d1[5], d1[4], d1[3], d1[2], d1[1]);
+        // p-: left-biased on the window d1[0..4]; p+: right-biased on d1[1..5]
+        const WenoR<T> rl = weno_window(d1[0], d1[1], d1[2], d1[3], d1[4]);
+        pm = weno_blend(d1[0], d1[1], d1[2], d1[3], d1[4], rl.ra, rl.rb, rl.rc);
+        const WenoR<T> rr = weno_window(d1[1], d1[2], d1[3], d1[4], d1[5]);
+        pp = weno_blend(d1[5], d1[4], d1[3], d1[2], d1[1], rr.rc, rr.rb, rr.ra);
     }
 }
 
@@ -199,12 +229,13 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
         axis_derivs<T, SCH>(a.vs, node, ii[d], int(a.n[d]), a.stride[d], (a.periodic >> d) & 1u,
                             a.dx[d], a.inv_dx[d], a.inv_2dx[d], pm[d], pp[d], center);
     T pbar[D];
+    T diss = T(0);
 #pragma unroll
-    for (int d = 0; d < D; ++d) pbar[d] = (pp[d] + pm[d]) * T(0.5);
-    T h = hamiltonian<T, D, DYN>(a, ii, pbar);
-#pragma unroll
-    for (int d = 0; d < D; ++d) h -= a.alpha[d] * ((pp[d] - pm[d]) * T(0.5));
-    const T l = -h;
+    for (int d = 0; d < D; ++d) {
+        pbar[d] = (pp[d] + pm[d]) * T(0.5);
+        diss += a.alpha[d] * ((pp[d] - pm[d]) * T(0.5));
+    }
+    const T l = -(hamiltonian<T, D, DYN>(a, ii, pbar) - diss);
 
     T val;
     if (a.combine == kRhs) {
@@ -227,62 +258,5 @@ __global__ __launch_bounds__(256) void stage_kernel(const StageArgs<T> a)
     if (node >= a.total) return;
     stage_node<T, D, SCH, DYN>(a, node);
 }
-
-template <typename T, int D, int SCH, int DYN>
-hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
-{
-    const uint32_t blocks = (a.total + 255u) / 256u;
-    hipLaunchKernelGGL((stage_kernel<T, D, SCH, DYN>), dim3(blocks), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-// SPACES: bit mask of the derivative schemes this translation unit builds
-// (1 << scheme); the others return hipErrorInvalidValue.
-template <typename T, int D, int DYN, unsigned SPACES>
-hipError_t launch_space(int space, const StageArgs<T> &a, hipStream_t s)
-{
-    if constexpr ((SPACES >> kUpwind1) & 1u)
-        if (space == kUpwind1) return launch_one<T, D, kUpwind1, DYN>(a, s);
-    if constexpr ((SPACES >> kEno2) & 1u)
-        if (space == kEno2) return launch_one<T, D, kEno2, DYN>(a, s);
-    if constexpr ((SPACES >> kWeno5) & 1u)
-        if (space == kWeno5) return launch_one<T, D, kWeno5, DYN>(a, s);
-    return hipErrorInvalidValue;
-}
-
-template <typename T, unsigned SPACES>
-hipError_t launch_stage_t(int ndim, int space, int dyn, const StageArgs<T> &a, hipStream_t s)
-{
-    switch (dyn) {
-    case kTranslation:
-        switch (ndim) {
-        case 1: return launch_space<T, 1, kTranslation, SPACES>(space, a, s);
-        case 2: return launch_space<T, 2, kTranslation, SPACES>(space, a, s);
-        case 3: return launch_space<T, 3, kTranslation, SPACES>(space, a, s);
-        case 4: return launch_space<T, 4, kTranslation, SPACES>(space, a, s);
-        }
-        break;
-    case kBall:
-        switch (ndim) {
-        case 1: return launch_space<T, 1, kBall, SPACES>(space, a, s);
-        case 2: return launch_space<T, 2, kBall, SPACES>(space, a, s);
-        case 3: return launch_space<T, 3, kBall, SPACES>(space, a, s);
-        case 4: return launch_space<T, 4, kBall, SPACES>(space, a, s);
-        }
-        break;
-    case kDoubleIntegrator:
-        if (ndim == 2) return launch_space<T, 2, kDoubleIntegrator, SPACES>(space, a, s);
-        break;
-    case kRelDubins:
-        if (ndim == 3) return launch_space<T, 3, kRelDubins, SPACES>(space, a, s);
-        break;
-    case kDubins4D:
-        if (ndim == 4) return launch_space<T, 4, kDubins4D, SPACES>(space, a, s);
-        break;
-    }
-    return hipErrorInvalidValue;
-}
-
-constexpr unsigned kAllSpaces = (1u << kUpwind1) | (1u << kEno2) | (1u << kWeno5);
 
 }  // namespace hj

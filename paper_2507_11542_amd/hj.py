@@ -57,6 +57,7 @@ def _load():
     lib.hj_set_scheme.argtypes = [P, I, I, D]
     lib.hj_solve.argtypes = [P, P, P, D, D, I, P]
     lib.hj_step.argtypes = [P, P, P, PD, D, I, PD, P]
+    lib.hj_solve_mixed.argtypes = [P, P, P, D, D, I, D, P]
     lib.hj_rhs.argtypes = [P, P, P, P]
     lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
     lib.hj_grid_destroy.argtypes = [P]
@@ -71,6 +72,7 @@ def _load():
     lib.hj_batch_wait.argtypes = [P, P, PD, PI64]
     lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
+                 "hj_solve_mixed",
                  "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_grid_set_workspace",
                  "hj_batch_create",
                  "hj_batch_config", "hj_solve_batch", "hj_step_batch", "hj_batch_wait",
@@ -144,6 +146,12 @@ def hj_set_scheme(g, space: int = HJ_WENO5, time: int = HJ_RK3, cfl: float = 0.8
 def hj_solve(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, stream=None):
     _check(_lib.hj_solve(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
                          _stream(stream)))
+
+
+def hj_solve_mixed(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, band: float = -1.0,
+                   stream=None):
+    _check(_lib.hj_solve_mixed(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
+                               float(band), _stream(stream)))
 
 
 def hj_step(g, V, V0, t: float, tf: float, mode: int = HJ_SET, stream=None
@@ -293,6 +301,9 @@ class Grid:
 
     def step(self, V, V0, t, tf, mode="set", stream=None):
         return hj_step(self.handle, V, V0, t, tf, MODE[mode], stream)
+
+    def solve_mixed(self, V0, V_out, t0, tf, mode="set", band=-1.0, stream=None):
+        hj_solve_mixed(self.handle, V0, V_out, t0, tf, MODE[mode], band, stream)
 
     def rhs(self, V, L_out, stream=None):
         hj_rhs(self.handle, V, L_out, stream)

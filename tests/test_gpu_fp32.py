@@ -47,3 +47,35 @@ def test_fp32_zero_set_and_front(orc, name, p):
     assert hd <= 0.5
     assert errs["band_inner"] <= 1e-4
     assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("name,p", CASES[:1] + CASES[2:], ids=["rel_dubins_51", "double_integrator_201"])
+def test_mixed_precision_tube(orc, name, p):
+    """hj_solve_mixed: FP64 in and out, FP32 bulk, tube minimum retaken in FP64
+    on the band |V| <= 3 max(dx).  Outside the band it is the FP32 solve
+    widened; inside, min(V32, V0) with the exact V0."""
+    import torch
+
+    from gpu_util import gpu_solve, oracle_solve
+    from paper_2507_11542_amd import hj
+
+    v0 = p.v0()
+    d0 = torch.from_numpy(v0).to("cuda")
+    out = torch.empty_like(d0)
+    g = hj.Grid.from_problem(p, "fp32")
+    try:
+        g.solve_mixed(d0, out, p.t0, p.tf, p.mode, -1.0, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+    finally:
+        g.close()
+    got = out.cpu().numpy()
+    plain32 = gpu_solve(p, "fp32", v0=v0)
+    dx = inputs.cell_sizes(*p.grid_args())
+    band = np.abs(plain32) <= 3 * dx.max()
+    assert np.array_equal(got[~band], plain32[~band])
+    assert np.array_equal(got[band], np.minimum(plain32[band], v0[band]))
+    ref, *_ = oracle_solve(orc, p)
+    errs = metrics.region_errors(got, ref, dx, p.periodic)
+    hd = metrics.hausdorff_cells(got, ref, p.periodic)
+    print(json.dumps({"case": name, "mixed": True, "hausdorff_cells": hd, **errs}), flush=True)
+    assert hd <= 0.5 and errs["band_inner"] <= 1e-4
