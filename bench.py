@@ -36,17 +36,26 @@ HBM_PEAK_GBS = 8000.0
 # x1.000), keyed by precision, with the hash of the kernel sources they were
 # taken on; a changed source reports null until the counters are re-taken.
 MEASURED_TRAFFIC = {
-    "fp64": {"src_hash": "3585621594a2fdbd", "fetch_kib": 17593.6, "write_kib": 8049.2,
+    "fp64": {"src_hash": "86d0846449fe6114", "fetch_kib": 17609.2, "write_kib": 8049.2,
+             "fetch_scale": 2.0, "write_scale": 1.0},
+    "fp32": {"src_hash": "86d0846449fe6114", "fetch_kib": 9070.1, "write_kib": 4024.6,
              "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
+# the sources the per-node stage kernel is compiled from, and its build flags
+STAGE_KERNEL_SOURCES = ("hj_internal.h", "hj_stage_impl.h", "hj_launch_impl.h",
+                        "hj_stage_f64_exact.hip", "hj_stage_f32.hip")
+
+
 def source_hash() -> str:
-    import glob
     import hashlib
 
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2507_11542_amd", "csrc", "*"))):
+    pkg = os.path.join(ROOT, "paper_2507_11542_amd")
+    paths = [os.path.join(pkg, "csrc", f) for f in STAGE_KERNEL_SOURCES]
+    paths.append(os.path.join(pkg, "build_lib.py"))
+    for f in paths:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
