@@ -185,7 +185,8 @@ def bench_served(args):
         be = GpuBackend(prec="fp32", v0_cache=v0_cache)
         try:
             rep, _ = Server(be, hbm_budget=int(args.serve_budget_gib * (1 << 30)),
-                            macro_steps=args.macro_steps).run(at_rate(rate))
+                            macro_steps=args.macro_steps,
+                            macro_updates=args.macro_updates).run(at_rate(rate))
         finally:
             be.close()
         return rep.as_dict()
@@ -204,6 +205,7 @@ def bench_served(args):
         plains["%.2fx" % f] = dict(plain(f * lam_sat), rate_req_per_s=f * lam_sat)
     return {"workload": "%d requests, thirds DI 101^2..401^2 / rel-Dubins 51^3..121^3 / "
                         "4-D Dubins 41^4..61^4, WENO5+LF+RK3, FP32, Poisson (seed 0)" % n,
+            "macro_steps": args.macro_steps, "macro_updates": args.macro_updates,
             "saturated_rate_req_per_s": lam_sat, "served": runs, "plain": plains,
             "served_vs_plain_updates_per_s":
                 sat["updates_per_s"] / plains["saturated"]["updates_per_s"]}
@@ -224,7 +226,10 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.5, 0.9])
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
-    ap.add_argument("--macro-steps", type=int, default=32)
+    ap.add_argument("--macro-steps", type=int, default=64,
+                    help="most RK steps per instance in one serving macro-iteration")
+    ap.add_argument("--macro-updates", type=float, default=1.5e8,
+                    help="node-steps a family's serving macro-iteration aims at")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates "
                          "the HBM byte counters of a profiler run)")

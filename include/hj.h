@@ -152,11 +152,19 @@ typedef struct hj_batch_s *hj_batch_t;
 /* New batch engine on the current device. */
 hj_status hj_batch_create(hj_batch_t *out);
 
-/* Launch shape: tile_nodes the largest tile (multiple of 256, in
- * [256, 2^22]; default 4096; an instance's tiles shrink, in steps of 256, so
- * that it has at least 512 of them when it can), workgroups of 256 threads per round launch striding over the
- * round's tiles (in [1, 65536]; default 1024), use_graph != 0 to replay a
- * captured hipGraph (default) instead of direct launches. */
+/* Launch shape.  workgroups == 0 (the default) selects flat launches: every
+ * round launch has one 256-thread workgroup per 256-node tile of the round
+ * (one node per thread), and tile_nodes is ignored.  workgroups in
+ * [1, 65536] selects strided launches: that many workgroups per round stride
+ * over the round's tiles, each tile up to tile_nodes nodes (a multiple of
+ * 256 in [256, 2^22]; an instance's tiles shrink, in steps of 256, so that
+ * it has at least 512 of them when it can).  tile_nodes is checked in both
+ * cases.  use_graph != 0 (default) replays a captured hipGraph instead of
+ * launching directly: the handle keeps up to 16 graphs, each captured for one
+ * kernel variant, launch shape and round count (flat launches: with each
+ * round's workgroup count rounded up to one of 8 sizes per power of two) and
+ * replayed by any batch that fits it, and captures a new one when none does.
+ * HJ_E_ARG out of range. */
 hj_status hj_batch_config(hj_batch_t b, int tile_nodes, int workgroups, int use_graph);
 
 /* Solve instance i from V0s[i] over [t0[i], tf[i]] in modes[i] into Vouts[i]

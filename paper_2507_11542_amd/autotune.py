@@ -14,8 +14,10 @@ import math
 import os
 from typing import Dict, List, Optional, Sequence, Tuple
 
+# (nodes per tile, workgroups per round launch); workgroups 0 = flat launches
+# (one workgroup per 256-node tile)
 CANDIDATES: Tuple[Tuple[int, int], ...] = (
-    (1024, 1024), (1024, 2048), (2048, 1024), (2048, 2048), (4096, 512), (4096, 1024),
+    (256, 0), (1024, 1024), (1024, 2048), (2048, 1024), (2048, 2048), (4096, 512), (4096, 1024),
     (4096, 2048), (8192, 1024), (8192, 2048), (16384, 1024),
 )
 

@@ -3,8 +3,10 @@
 // advanced together, one fused launch per RK-stage round over every running
 // instance (hj_batch_impl.h).  The sequence of round launches is captured once
 // in a hipGraph and replayed; every table the kernels read lives in device
-// memory, so a new batch composition only needs uploads before the replay
-// (and a new capture only when it needs more rounds than were captured).
+// memory, so a new batch composition only needs uploads before the replay.
+// The handle keeps a few captured graphs, each for one kernel variant, launch
+// shape and round count (flat launches: with per-round workgroup counts that
+// a replayed batch must not exceed), and captures a new one when none fits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,28 +24,28 @@ using namespace hj;
 
 namespace hj {
 hipError_t batch_launch_f64(int ndim, int space, int dyn, const BatchPtrs<double> &p,
-                            uint32_t rounds, uint32_t workgroups, hipStream_t s);
+                            uint32_t rounds, const BatchShape &shape, hipStream_t s);
 hipError_t batch_launch_f32(int ndim, int space, int dyn, const BatchPtrs<float> &p,
-                            uint32_t rounds, uint32_t workgroups, hipStream_t s);
+                            uint32_t rounds, const BatchShape &shape, hipStream_t s);
 }  // namespace hj
 
 struct hj_batch_s {
     int device = 0;
-    uint32_t tile_nodes = 4096;
-    uint32_t workgroups = 1024;
+    uint32_t tile_nodes = 256;
+    uint32_t workgroups = 0;   // 0: flat launches (one workgroup per 256-node tile)
     bool use_graph = true;
 
     // device tables and their capacities
-    uint32_t cap_inst = 0, cap_rounds = 0;
+    uint32_t cap_inst = 0, cap_rounds = 0, cap_tiles = 0;
     void *inst = nullptr;        // BatchInst<T>[cap_inst]
     BatchCtl *ctl = nullptr;     // [cap_inst]
-    uint32_t *sorted = nullptr;  // [cap_inst]
-    uint32_t *tile_pre = nullptr;   // [cap_inst + 1]
+    TileRef *tile_map = nullptr;    // [cap_tiles]
     uint32_t *round_off = nullptr;  // [cap_rounds + 1]
     BatchGlobal *gl = nullptr;
     // pinned host staging
     void *h_inst = nullptr;
-    uint32_t *h_sorted = nullptr, *h_tile_pre = nullptr, *h_round_off = nullptr;
+    TileRef *h_tile_map = nullptr;
+    uint32_t *h_round_off = nullptr;
     BatchGlobal *h_gl = nullptr;
     BatchCtl *h_ctl_out = nullptr;    // read back after a solve
     uint32_t last_n = 0;
@@ -53,11 +55,18 @@ struct hj_batch_s {
     hipEvent_t done_evt = nullptr;
     bool pending = false;
 
-    // captured graph and the launch it was captured for
-    hipGraphExec_t exec = nullptr;
+    // captured graphs and the launches they were captured for
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        int nd = -1, space = -1, dyn = -1, prec = -1;
+        uint32_t wg = 0, rounds = 0;
+        std::vector<uint32_t> grid;  // flat: workgroups of each round
+        uint64_t used = 0;           // last use (LRU)
+    };
+    std::vector<Graph> graphs;
+    uint64_t clock = 0;
     hipStream_t capture_stream = nullptr;
-    int key_nd = -1, key_space = -1, key_dyn = -1, key_prec = -1;
-    uint32_t key_wg = 0, key_rounds = 0;
+    std::vector<uint32_t> round_grid;  // scratch: workgroups per round
 };
 
 namespace {
@@ -71,28 +80,31 @@ void free_tables(hj_batch_t b)
 {
     if (b->inst) (void)hipFree(b->inst);
     if (b->ctl) (void)hipFree(b->ctl);
-    if (b->sorted) (void)hipFree(b->sorted);
-    if (b->tile_pre) (void)hipFree(b->tile_pre);
+    if (b->tile_map) (void)hipFree(b->tile_map);
     if (b->round_off) (void)hipFree(b->round_off);
     if (b->h_inst) (void)hipHostFree(b->h_inst);
-    if (b->h_sorted) (void)hipHostFree(b->h_sorted);
-    if (b->h_tile_pre) (void)hipHostFree(b->h_tile_pre);
+    if (b->h_tile_map) (void)hipHostFree(b->h_tile_map);
     if (b->h_round_off) (void)hipHostFree(b->h_round_off);
     if (b->h_ctl_out) (void)hipHostFree(b->h_ctl_out);
-    b->inst = b->ctl = nullptr;
-    b->sorted = b->tile_pre = b->round_off = nullptr;
+    b->inst = nullptr;
+    b->ctl = nullptr;
+    b->tile_map = nullptr;
+    b->round_off = nullptr;
     b->h_inst = nullptr;
-    b->h_sorted = b->h_tile_pre = b->h_round_off = nullptr;
+    b->h_tile_map = nullptr;
+    b->h_round_off = nullptr;
     b->h_ctl_out = nullptr;
-    b->cap_inst = b->cap_rounds = 0;
+    b->cap_inst = b->cap_rounds = b->cap_tiles = 0;
 }
 
 void drop_graph(hj_batch_t b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-    b->key_nd = -1;
+    for (auto &g : b->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
 }
+
+constexpr size_t kMaxGraphs = 16;
 
 hj_status host_alloc(void **p, size_t bytes, const char *what)
 {
@@ -100,12 +112,17 @@ hj_status host_alloc(void **p, size_t bytes, const char *what)
     return HJ_OK;
 }
 
-// Grow the tables to hold n instances and `rounds` rounds.  Any change of a
-// device address invalidates the captured graph.
-hj_status reserve(hj_batch_t b, uint32_t n, uint32_t rounds)
+// Grow the tables to hold n instances, `rounds` rounds and `tiles` tiles per
+// round (the tile map grows by at least half its size).  Any change of a
+// device address invalidates the captured graphs.
+hj_status reserve(hj_batch_t b, uint32_t n, uint32_t rounds, uint32_t tiles)
 {
-    if (n <= b->cap_inst && rounds <= b->cap_rounds) return HJ_OK;
+    if (n <= b->cap_inst && rounds <= b->cap_rounds && tiles <= b->cap_tiles) return HJ_OK;
     const uint32_t ci = std::max(n, b->cap_inst), cr = std::max(rounds, b->cap_rounds);
+    const uint32_t ct = tiles <= b->cap_tiles
+                            ? b->cap_tiles
+                            : uint32_t(std::min<uint64_t>(
+                                  0xffffffffu, std::max<uint64_t>(tiles, b->cap_tiles * 3ull / 2)));
     drop_graph(b);
     free_tables(b);
     hj_status s;
@@ -113,18 +130,13 @@ hj_status reserve(hj_batch_t b, uint32_t n, uint32_t rounds)
     if ((s = dev_alloc(&b->inst, isz * ci, "batch instance table")) != HJ_OK) return s;
     if ((s = dev_alloc((void **)&b->ctl, sizeof(BatchCtl) * ci, "batch control")) != HJ_OK)
         return s;
-    if ((s = dev_alloc((void **)&b->sorted, sizeof(uint32_t) * ci, "batch order")) != HJ_OK)
-        return s;
-    if ((s = dev_alloc((void **)&b->tile_pre, sizeof(uint32_t) * (ci + 1), "batch tiles")) !=
-        HJ_OK)
+    if ((s = dev_alloc((void **)&b->tile_map, sizeof(TileRef) * ct, "batch tile map")) != HJ_OK)
         return s;
     if ((s = dev_alloc((void **)&b->round_off, sizeof(uint32_t) * (cr + 1), "batch rounds")) !=
         HJ_OK)
         return s;
     if ((s = host_alloc(&b->h_inst, isz * ci, "pinned instance table")) != HJ_OK) return s;
-    if ((s = host_alloc((void **)&b->h_sorted, sizeof(uint32_t) * ci, "pinned order")) != HJ_OK)
-        return s;
-    if ((s = host_alloc((void **)&b->h_tile_pre, sizeof(uint32_t) * (ci + 1), "pinned tiles")) !=
+    if ((s = host_alloc((void **)&b->h_tile_map, sizeof(TileRef) * ct, "pinned tile map")) !=
         HJ_OK)
         return s;
     if ((s = host_alloc((void **)&b->h_round_off, sizeof(uint32_t) * (cr + 1),
@@ -135,6 +147,7 @@ hj_status reserve(hj_batch_t b, uint32_t n, uint32_t rounds)
         return s;
     b->cap_inst = ci;
     b->cap_rounds = cr;
+    b->cap_tiles = ct;
     return HJ_OK;
 }
 
@@ -144,63 +157,102 @@ BatchPtrs<T> ptrs(hj_batch_t b)
     BatchPtrs<T> p;
     p.inst = (const BatchInst<T> *)b->inst;
     p.ctl = b->ctl;
-    p.sorted = b->sorted;
-    p.tile_pre = b->tile_pre;
+    p.tile_map = b->tile_map;
     p.round_off = b->round_off;
     p.gl = b->gl;
     return p;
 }
 
 hipError_t launch_any(hj_batch_t b, int nd, int space, int dyn, hj_precision prec,
-                      uint32_t rounds, hipStream_t s)
+                      uint32_t rounds, const BatchShape &sh, hipStream_t s)
 {
-    if (prec == HJ_FP64)
-        return batch_launch_f64(nd, space, dyn, ptrs<double>(b), rounds, b->workgroups, s);
-    return batch_launch_f32(nd, space, dyn, ptrs<float>(b), rounds, b->workgroups, s);
+    if (prec == HJ_FP64) return batch_launch_f64(nd, space, dyn, ptrs<double>(b), rounds, sh, s);
+    return batch_launch_f32(nd, space, dyn, ptrs<float>(b), rounds, sh, s);
 }
 
-// The init kernel and the round launches, captured once per kernel variant,
-// launch width and round capacity; replays read the current tables and skip
-// the captured rounds beyond the batch's own.
+// Flat launches in a graph: a round's workgroup count rounded up so that
+// about 8 sizes per power of two share one capture.
+uint32_t grid_capacity(uint32_t tiles)
+{
+    if (tiles == 0) return 1;
+    uint32_t q = 1;
+    while (q * 16u <= tiles) q <<= 1;  // tiles / 16 < q <= tiles / 8 (for tiles >= 16)
+    const uint64_t c = (uint64_t(tiles) + q - 1) / q * q;
+    return c > 0x7fffffffu ? 0x7fffffffu : uint32_t(c);
+}
+
+// Launches the init kernel and the batch's rounds: directly, or by replaying
+// a captured graph of the same kernel variant, launch shape and round count
+// whose per-round workgroups (flat launches) cover the batch's tiles of
+// every round, captured on demand (least recently used one dropped beyond
+// kMaxGraphs).  The round tables (h_round_off) are the batch's.
 hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, uint32_t rounds,
               hipStream_t s)
 {
+    const bool flat = b->workgroups == 0;
+    std::vector<uint32_t> &grid = b->round_grid;
+    grid.assign(flat ? rounds : 0, 0u);
+    for (uint32_t r = 0; flat && r < rounds; ++r)
+        grid[r] = b->h_round_off[r + 1] - b->h_round_off[r];
     if (!b->use_graph) {
-        hipError_t e = launch_any(b, nd, space, dyn, prec, rounds, s);
+        const BatchShape sh{b->workgroups, grid.data()};
+        hipError_t e = launch_any(b, nd, space, dyn, prec, rounds, sh, s);
         if (e != hipSuccess) return hip_fail(e, "batch launch");
         return HJ_OK;
     }
-    if (!(b->exec && b->key_nd == nd && b->key_space == space && b->key_dyn == dyn &&
-          b->key_prec == prec && b->key_wg == b->workgroups && rounds <= b->key_rounds)) {
-        drop_graph(b);
-        const uint32_t cap = (rounds + 63u) & ~63u;
+    hj_batch_s::Graph *hit = nullptr;
+    for (auto &g : b->graphs) {
+        if (g.nd != nd || g.space != space || g.dyn != dyn || g.prec != prec ||
+            g.wg != b->workgroups || g.rounds != rounds)
+            continue;
+        bool fits = true;
+        for (uint32_t r = 0; flat && r < rounds && fits; ++r) fits = grid[r] <= g.grid[r];
+        if (fits) {
+            hit = &g;
+            break;
+        }
+    }
+    if (!hit) {
+        hj_batch_s::Graph g;
+        g.nd = nd;
+        g.space = space;
+        g.dyn = dyn;
+        g.prec = prec;
+        g.wg = b->workgroups;
+        g.rounds = rounds;
+        g.grid.resize(grid.size());
+        for (size_t r = 0; r < grid.size(); ++r) g.grid[r] = grid_capacity(grid[r]);
         if (!b->capture_stream)
             HJ_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking),
                    "capture stream");
         hipGraph_t graph = nullptr;
         HJ_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal),
                "begin capture");
-        hipError_t e = launch_any(b, nd, space, dyn, prec, cap, b->capture_stream);
+        const BatchShape sh{b->workgroups, g.grid.data()};
+        hipError_t e = launch_any(b, nd, space, dyn, prec, rounds, sh, b->capture_stream);
         hipError_t e2 = hipStreamEndCapture(b->capture_stream, &graph);
         if (e != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
             return hip_fail(e, "batch launch (capture)");
         }
         if (e2 != hipSuccess) return hip_fail(e2, "end capture");
-        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            b->exec = nullptr;
-            return hip_fail(e, "graph instantiate");
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+        if (b->graphs.size() >= kMaxGraphs) {
+            auto lru = std::min_element(
+                b->graphs.begin(), b->graphs.end(),
+                [](const hj_batch_s::Graph &x, const hj_batch_s::Graph &y) {
+                    return x.used < y.used;
+                });
+            (void)hipGraphExecDestroy(lru->exec);
+            b->graphs.erase(lru);
         }
-        b->key_nd = nd;
-        b->key_space = space;
-        b->key_dyn = dyn;
-        b->key_prec = prec;
-        b->key_wg = b->workgroups;
-        b->key_rounds = cap;
+        b->graphs.push_back(std::move(g));
+        hit = &b->graphs.back();
     }
-    HJ_HIP(hipGraphLaunch(b->exec, s), "graph launch");
+    hit->used = ++b->clock;
+    HJ_HIP(hipGraphLaunch(hit->exec, s), "graph launch");
     return HJ_OK;
 }
 
@@ -274,7 +326,8 @@ hj_status hj_batch_config(hj_batch_t b, int tile_nodes, int workgroups, int use_
     if (!b) return fail(HJ_E_ARG, "null batch handle");
     if (tile_nodes < 256 || tile_nodes > (1 << 22) || (tile_nodes & 255))
         return fail(HJ_E_ARG, "tile_nodes must be a multiple of 256 in [256, 2^22]");
-    if (workgroups < 1 || workgroups > 65536) return fail(HJ_E_ARG, "workgroups in [1, 65536]");
+    if (workgroups < 0 || workgroups > 65536)
+        return fail(HJ_E_ARG, "workgroups in [0, 65536] (0: flat launches)");
     if (b->workgroups != uint32_t(workgroups)) drop_graph(b);
     b->tile_nodes = uint32_t(tile_nodes);
     b->workgroups = uint32_t(workgroups);
@@ -362,7 +415,7 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
             }
         steps[i] = k;
         if (t_reached) t_reached[i] = t;
-        tsize[i] = instance_tile(uint32_t(gs[i]->total), b->tile_nodes);
+        tsize[i] = b->workgroups ? instance_tile(uint32_t(gs[i]->total), b->tile_nodes) : 256u;
         tiles[i] = uint32_t((gs[i]->total + tsize[i] - 1) / tsize[i]);
         max_n = std::max(max_n, steps[i]);
     }
@@ -370,24 +423,26 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
     const uint64_t rounds64 = uint64_t(order) * max_n;
     if (rounds64 >= (uint64_t(1) << 31)) return fail(HJ_E_ARG, "too many steps");
     const uint32_t rounds = uint32_t(rounds64);
-    if ((s = reserve(b, uint32_t(n), rounds)) != HJ_OK) return s;
-
     // instances by step count, descending: the active ones form a prefix
     std::vector<uint32_t> ord(n);
     std::iota(ord.begin(), ord.end(), 0u);
     std::stable_sort(ord.begin(), ord.end(),
                      [&](uint32_t x, uint32_t y) { return steps[x] > steps[y]; });
-    b->h_tile_pre[0] = 0;
+    std::vector<uint32_t> pre(n + 1, 0u);  // tiles of the first k sorted instances
     for (int k = 0; k < n; ++k) {
-        b->h_sorted[k] = ord[k];
-        b->h_tile_pre[k + 1] = b->h_tile_pre[k] + tiles[ord[k]];
+        const uint64_t next = uint64_t(pre[k]) + tiles[ord[k]];
+        if (next > 0x7fffffffu) return fail(HJ_E_ARG, "too many tiles");
+        pre[k + 1] = uint32_t(next);
     }
+    if ((s = reserve(b, uint32_t(n), rounds, pre[n])) != HJ_OK) return s;
+    for (int k = 0; k < n; ++k)
+        for (uint32_t t = 0; t < tiles[ord[k]]; ++t) b->h_tile_map[pre[k] + t] = {ord[k], t};
     uint64_t total = 0;
     uint32_t active = uint32_t(n);
     for (uint32_t r = 0; r < rounds; ++r) {
         while (active > 0 && uint64_t(order) * steps[ord[active - 1]] <= r) --active;
         b->h_round_off[r] = uint32_t(total);
-        total += b->h_tile_pre[active];
+        total += pre[active];
         if (total >= (uint64_t(1) << 32) - 1) return fail(HJ_E_ARG, "too many work items");
     }
     b->h_round_off[rounds] = uint32_t(total);
@@ -412,10 +467,7 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
     b->h_gl->order = order;
 
     HJ_HIP(hipMemcpyAsync(b->inst, b->h_inst, isz * n, hipMemcpyHostToDevice, st), "upload");
-    HJ_HIP(hipMemcpyAsync(b->sorted, b->h_sorted, sizeof(uint32_t) * n, hipMemcpyHostToDevice,
-                          st),
-           "upload");
-    HJ_HIP(hipMemcpyAsync(b->tile_pre, b->h_tile_pre, sizeof(uint32_t) * (n + 1),
+    HJ_HIP(hipMemcpyAsync(b->tile_map, b->h_tile_map, sizeof(TileRef) * pre[n],
                           hipMemcpyHostToDevice, st),
            "upload");
     HJ_HIP(hipMemcpyAsync(b->round_off, b->h_round_off, sizeof(uint32_t) * (rounds + 1),

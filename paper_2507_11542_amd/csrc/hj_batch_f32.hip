@@ -3,8 +3,8 @@
 
 namespace hj {
 hipError_t batch_launch_f32(int ndim, int space, int dyn, const BatchPtrs<float> &p,
-                            uint32_t rounds, uint32_t workgroups, hipStream_t s)
+                            uint32_t rounds, const BatchShape &shape, hipStream_t s)
 {
-    return batch_launch_t<float>(ndim, space, dyn, p, rounds, workgroups, s);
+    return batch_launch_t<float>(ndim, space, dyn, p, rounds, shape, s);
 }
 }  // namespace hj

@@ -5,8 +5,8 @@
 
 namespace hj {
 hipError_t batch_launch_f64(int ndim, int space, int dyn, const BatchPtrs<double> &p,
-                            uint32_t rounds, uint32_t workgroups, hipStream_t s)
+                            uint32_t rounds, const BatchShape &shape, hipStream_t s)
 {
-    return batch_launch_t<double>(ndim, space, dyn, p, rounds, workgroups, s);
+    return batch_launch_t<double>(ndim, space, dyn, p, rounds, shape, s);
 }
 }  // namespace hj

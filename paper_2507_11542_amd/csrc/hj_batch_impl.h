@@ -5,7 +5,8 @@
 // by step count (descending), so the instances still running in round r are
 // a prefix of that order; the round's work is the concatenation of their
 // tiles (each instance's own tile size: the configured maximum, shrunk so a
-// small instance still spreads over enough workgroups).  The round kernel's workgroups stride over
+// small instance still spreads over enough workgroups), and tile k of every
+// round is the same (instance, tile) pair, listed once in a tile map.  The round kernel's workgroups stride over
 // those tiles; the kernel boundary between rounds is the only barrier, so no
 // workgroup ever waits on another.  All rounds are launched back to back (and
 // captured once in a hipGraph by the host), each kernel reading the round
@@ -34,6 +35,11 @@ struct BatchInst {
     int tube;
 };
 
+struct TileRef {
+    uint32_t inst;     // instance id (original order)
+    uint32_t tile;     // tile index within the instance
+};
+
 struct BatchCtl {
     double t[2];       // t at the start of even / odd steps
 };
@@ -51,9 +57,9 @@ template <typename T>
 struct BatchPtrs {
     const BatchInst<T> *inst;  // [ninst], original order
     BatchCtl *ctl;             // [ninst]
-    const uint32_t *sorted;    // [ninst] instance ids by step count, descending
-    const uint32_t *tile_pre;  // [ninst + 1] prefix sums of tiles over `sorted`
-    const uint32_t *round_off; // [rounds + 1] first tile of each round
+    const TileRef *tile_map;   // [tiles of round 0] tiles of the instances by step
+                               // count, descending; round r runs a prefix of it
+    const uint32_t *round_off; // [rounds + 1] first work item of each round
     const BatchGlobal *gl;
 };
 
@@ -65,20 +71,6 @@ __global__ __launch_bounds__(256) void batch_init(BatchPtrs<T> p)
         p.ctl[i].t[0] = p.inst[i].t0;
         p.ctl[i].t[1] = p.inst[i].t0;
     }
-}
-
-// largest k in [0, n) with a[k] <= x (a[0] <= x, a ascending)
-__device__ inline uint32_t upper_index(const uint32_t *a, uint32_t n, uint32_t x)
-{
-    uint32_t lo = 0, hi = n;  // invariant: a[lo] <= x, answer in [lo, hi)
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a[mid] <= x)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
 }
 
 // Arguments of stage (r % order) of instance `inst` for round r, and the
@@ -134,27 +126,45 @@ __device__ inline StageArgs<T> batch_stage_args(const BatchPtrs<T> &p, uint32_t 
     return a;
 }
 
-// the item k of round r: its instance and tile
+// tile `local` of a round: its instance and tile (wave-uniform)
 template <typename T>
-__device__ inline void batch_item(const BatchPtrs<T> &p, uint32_t begin, uint32_t k,
-                                  uint32_t *inst, uint32_t *tile)
+__device__ inline void batch_item(const BatchPtrs<T> &p, uint32_t local, uint32_t *inst,
+                                  uint32_t *tile)
 {
-    const uint32_t local = k - begin;
-    const uint32_t s = upper_index(p.tile_pre, p.gl->ninst, local);
-    *inst = __builtin_amdgcn_readfirstlane(p.sorted[s]);
-    *tile = __builtin_amdgcn_readfirstlane(local - p.tile_pre[s]);
+    const TileRef t = p.tile_map[local];
+    *inst = __builtin_amdgcn_readfirstlane(t.inst);
+    *tile = __builtin_amdgcn_readfirstlane(t.tile);
 }
 
-template <typename T, int D, int SCH, int DYN>
+// Round r of the batch.  Strided form: the launch's workgroups stride over
+// the round's tiles, each tile a loop over its nodes.  Flat form (FLAT): one
+// workgroup per 256-node tile and one node per thread, no loop at all, so the
+// kernel keeps the register footprint of the plain stage kernel (the loops of
+// the strided form keep about twice the VGPRs live, halving occupancy);
+// workgroups beyond the round's tiles return at once.
+template <typename T, int D, int SCH, int DYN, bool FLAT>
 __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r)
 {
     if (r >= p.gl->rounds) return;  // rounds beyond this batch: nothing to do
     const uint32_t begin = p.round_off[r], end = p.round_off[r + 1];
     const uint32_t order = p.gl->order;
     const uint32_t stage = r % order, step = r / order;
+    if (FLAT) {
+        if (blockIdx.x >= end - begin) return;
+        uint32_t inst, tile;
+        batch_item(p, blockIdx.x, &inst, &tile);
+        double h, t_n;
+        const StageArgs<T> a = batch_stage_args(p, inst, r, &h, &t_n);
+        const uint32_t node = tile * 256u + threadIdx.x;
+        if (node < a.total) stage_node<T, D, SCH, DYN>(a, node);
+        // the other slot: read by no tile of this step
+        if (stage == order - 1 && tile == 0 && threadIdx.x == 0)
+            p.ctl[inst].t[(step + 1) & 1u] = t_n + h;
+        return;
+    }
     for (uint32_t k = begin + blockIdx.x; k < end; k += gridDim.x) {
         uint32_t inst, tile;
-        batch_item(p, begin, k, &inst, &tile);
+        batch_item(p, k - begin, &inst, &tile);
         double h, t_n;
         const StageArgs<T> a = batch_stage_args(p, inst, r, &h, &t_n);
         const uint32_t tn = p.inst[inst].tile_nodes;
@@ -162,23 +172,34 @@ __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r)
         const uint32_t last = first + tn < a.total ? first + tn : a.total;
         for (uint32_t node = first + threadIdx.x; node < last; node += 256)
             stage_node<T, D, SCH, DYN>(a, node);
-        // the other slot: read by no tile of this step
         if (stage == order - 1 && tile == 0 && threadIdx.x == 0)
             p.ctl[inst].t[(step + 1) & 1u] = t_n + h;
     }
 }
 
+// How the rounds are launched: workgroups > 0 selects the strided form with
+// that many workgroups per round; workgroups == 0 the flat form, with
+// round_grid[r] workgroups for round r (at least the round's tiles).
+struct BatchShape {
+    uint32_t workgroups;
+    const uint32_t *round_grid;  // host array [rounds], flat form only
+};
+
 // The init kernel and rounds [0, rounds) of the round kernel, back to back.
 template <typename T, int D, int SCH, int DYN>
-hipError_t batch_launch_one(const BatchPtrs<T> &p, uint32_t rounds, uint32_t workgroups,
+hipError_t batch_launch_one(const BatchPtrs<T> &p, uint32_t rounds, const BatchShape &sh,
                             hipStream_t s)
 {
     hipLaunchKernelGGL((batch_init<T>), dim3(1), dim3(256), 0, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (uint32_t r = 0; r < rounds; ++r) {
-        hipLaunchKernelGGL((batch_round<T, D, SCH, DYN>), dim3(workgroups), dim3(256), 0, s, p,
-                           r);
+        if (sh.workgroups)
+            hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, false>), dim3(sh.workgroups),
+                               dim3(256), 0, s, p, r);
+        else
+            hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, true>), dim3(sh.round_grid[r]),
+                               dim3(256), 0, s, p, r);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -186,8 +207,8 @@ hipError_t batch_launch_one(const BatchPtrs<T> &p, uint32_t rounds, uint32_t wor
 }
 
 template <typename T, int D, int DYN>
-hipError_t batch_launch_space(int space, const BatchPtrs<T> &p, uint32_t rounds, uint32_t wg,
-                              hipStream_t s)
+hipError_t batch_launch_space(int space, const BatchPtrs<T> &p, uint32_t rounds,
+                              const BatchShape &wg, hipStream_t s)
 {
     if (space == kEno2) return batch_launch_one<T, D, kEno2, DYN>(p, rounds, wg, s);
     if (space == kWeno5) return batch_launch_one<T, D, kWeno5, DYN>(p, rounds, wg, s);
@@ -196,7 +217,7 @@ hipError_t batch_launch_space(int space, const BatchPtrs<T> &p, uint32_t rounds,
 
 template <typename T>
 hipError_t batch_launch_t(int ndim, int space, int dyn, const BatchPtrs<T> &p, uint32_t rounds,
-                          uint32_t wg, hipStream_t s)
+                          const BatchShape &wg, hipStream_t s)
 {
     switch (dyn) {
     case kTranslation:

@@ -15,6 +15,26 @@
 
 namespace hj {
 
+// Device pointers taken into the global address space, so that loads and
+// stores through them are global (vector-memory) instructions whatever the
+// pointer's origin: a kernel argument, or a table in device memory (batched
+// launches), where the compiler would otherwise emit flat instructions, which
+// also wait on the LDS counter.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ inline const gmem<T> *global_ptr(const T *p)
+{
+    return (const gmem<T> *)p;
+}
+
+template <typename T>
+__device__ inline gmem<T> *global_ptr(T *p)
+{
+    return (gmem<T> *)p;
+}
+
 template <int SCH>
 struct Halo;
 template <>
@@ -114,7 +134,7 @@ __device__ inline T eno_pick(T a, T b)
 // whose own axis index is i.  Interior values are loaded; ghost values wrap
 // (periodic) or extrapolate linearly from the two end nodes (bounded).
 template <typename T>
-__device__ inline T line_value(const T *__restrict__ v, uint32_t node, int i, int j, int n,
+__device__ inline T line_value(const gmem<T> *__restrict__ v, uint32_t node, int i, int j, int n,
                                uint32_t stride, bool periodic)
 {
     const uint32_t base = node - uint32_t(i) * stride;
@@ -135,7 +155,7 @@ __device__ inline T line_value(const T *__restrict__ v, uint32_t node, int i, in
 // First divided differences use the reciprocal cell size 1/dx, second ones
 // 1/(2 dx) (both computed once on the host in FP64).
 template <typename T, int SCH>
-__device__ inline void axis_derivs(const T *__restrict__ v, uint32_t node, int i, int n,
+__device__ inline void axis_derivs(const gmem<T> *__restrict__ v, uint32_t node, int i, int n,
                                    uint32_t stride, bool periodic, T dx, T inv_dx, T inv_2dx,
                                    T &pm, T &pp, T &center)
 {
@@ -190,21 +210,21 @@ __device__ inline T hamiltonian(const StageArgs<T> &a, const int *ii, const T *p
         for (int d = 0; d < D; ++d) s += p[d] * p[d];
         return a.prm[0] * sqrt(s);
     } else if constexpr (DYN == kDoubleIntegrator) {
-        const T x2 = a.tab[a.tab_off[1] + ii[1]];
+        const T x2 = global_ptr(a.tab)[a.tab_off[1] + ii[1]];
         return -p[0] * x2 + a.prm[0] * fabs(p[1]);
     } else if constexpr (DYN == kRelDubins) {
         const T ve = a.prm[0], vp = a.prm[1], we = a.prm[2], wp = a.prm[3];
-        const T x = a.tab[a.tab_off[0] + ii[0]];
-        const T y = a.tab[a.tab_off[1] + ii[1]];
-        const T c = a.tab[a.tab_off[2] + a.n[2] + ii[2]];
-        const T s = a.tab[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+        const T x = global_ptr(a.tab)[a.tab_off[0] + ii[0]];
+        const T y = global_ptr(a.tab)[a.tab_off[1] + ii[1]];
+        const T c = global_ptr(a.tab)[a.tab_off[2] + a.n[2] + ii[2]];
+        const T s = global_ptr(a.tab)[a.tab_off[2] + 2 * a.n[2] + ii[2]];
         return -p[0] * (-ve + vp * c) - p[1] * (vp * s) - we * fabs(p[0] * y - p[1] * x - p[2]) +
                wp * fabs(p[2]);
     } else {
         const T wm = a.prm[0], am = a.prm[1];
-        const T c = a.tab[a.tab_off[2] + a.n[2] + ii[2]];
-        const T s = a.tab[a.tab_off[2] + 2 * a.n[2] + ii[2]];
-        const T v = a.tab[a.tab_off[3] + ii[3]];
+        const T c = global_ptr(a.tab)[a.tab_off[2] + a.n[2] + ii[2]];
+        const T s = global_ptr(a.tab)[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+        const T v = global_ptr(a.tab)[a.tab_off[3] + ii[3]];
         return -p[0] * (v * c) - p[1] * (v * s) + wm * fabs(p[2]) + am * fabs(p[3]);
     }
 }
@@ -226,8 +246,9 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
     T pm[D], pp[D], center = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        axis_derivs<T, SCH>(a.vs, node, ii[d], int(a.n[d]), a.stride[d], (a.periodic >> d) & 1u,
-                            a.dx[d], a.inv_dx[d], a.inv_2dx[d], pm[d], pp[d], center);
+        axis_derivs<T, SCH>(global_ptr(a.vs), node, ii[d], int(a.n[d]), a.stride[d],
+                            (a.periodic >> d) & 1u, a.dx[d], a.inv_dx[d], a.inv_2dx[d], pm[d],
+                            pp[d], center);
     T pbar[D];
     T diss = T(0);
 #pragma unroll
@@ -245,10 +266,10 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
         if (a.combine == kEuler)
             val = v2;
         else
-            val = (a.wb * a.vb[node] + a.w2 * v2) / a.den;
+            val = (a.wb * global_ptr(a.vb)[node] + a.w2 * v2) / a.den;
     }
-    if (a.tube) val = fmin(val, a.v0[node]);
-    a.out[node] = val;
+    if (a.tube) val = fmin(val, global_ptr(a.v0)[node]);
+    global_ptr(a.out)[node] = val;
 }
 
 template <typename T, int D, int SCH, int DYN>

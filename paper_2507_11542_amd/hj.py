@@ -190,7 +190,7 @@ def hj_batch_create() -> ctypes.c_void_p:
     return h
 
 
-def hj_batch_config(b, tile_nodes: int = 4096, workgroups: int = 1024, use_graph: bool = True):
+def hj_batch_config(b, tile_nodes: int = 256, workgroups: int = 0, use_graph: bool = True):
     _check(_lib.hj_batch_config(b, int(tile_nodes), int(workgroups), 1 if use_graph else 0))
 
 
@@ -241,11 +241,11 @@ def hj_batch_destroy(b):
 class Batch:
     """Owning wrapper of one hj_batch_t (marshalling only)."""
 
-    def __init__(self, tile_nodes=4096, workgroups=1024, use_graph=True):
+    def __init__(self, tile_nodes=256, workgroups=0, use_graph=True):
         self.handle = hj_batch_create()
         self.config(tile_nodes, workgroups, use_graph)
 
-    def config(self, tile_nodes=4096, workgroups=1024, use_graph=True):
+    def config(self, tile_nodes=256, workgroups=0, use_graph=True):
         self.tile_nodes, self.workgroups, self.use_graph = tile_nodes, workgroups, use_graph
         hj_batch_config(self.handle, tile_nodes, workgroups, use_graph)
 

@@ -4,16 +4,17 @@ Requests (a Problem: grid, dynamics, scheme, horizon, V0 recipe) arrive over
 time.  The server admits a request when it has arrived, a slot is free and
 its device bytes fit the HBM budget, and keeps every admitted solve resident
 on the device until it finishes.  Admitted requests are grouped by kernel
-family (ndim, dynamics, scheme, RK order, precision); every macro-iteration
-advances each family by up to `macro_steps` RK steps per instance with one
-batched launch sequence (hj_step_batch, replayed from one captured graph), the
-families on their own streams so their work overlaps on the device.  After a
-macro-iteration finished requests retire (their memory returns to the budget)
-and waiting requests join: requests arriving while others are on the GPU are
-admitted as slots and memory free up.
+family (ndim, dynamics, scheme, RK order, precision); a macro-iteration of a
+family advances every instance in it by up to `macro_steps` RK steps with one
+batched launch sequence (hj_step_batch, replayed from one captured graph).
+The families run on their own streams, so their work overlaps on the device,
+and progress independently: when a family's macro-iteration completes, its
+finished requests retire (their memory returns to the budget), waiting
+requests are admitted as slots and memory free up, and the family is
+relaunched with the requests that joined it.
 
 Scheduling is separate from the device: `Server` drives a backend with
-`bytes_needed / admit / advance / sync / release`; `GpuBackend` implements it
+`bytes_needed / admit / advance / ready / release`; `GpuBackend` implements it
 with libhj through its C ABI (torch for device memory and streams).  The
 per-request results equal those of a request solved alone (the batched kernels
 run the same per-node arithmetic with the same FP64 step sizes).
@@ -22,6 +23,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import math
 import time
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -93,22 +95,47 @@ def report(jobs: List[Job], makespan: float, max_active: int, peak: int, iters: 
 
 
 class Server:
-    """Admission by device bytes and slots, continuous batching by family."""
+    """Admission by device bytes and slots, continuous batching by family.
+
+    Families progress independently: each has at most one macro-iteration in
+    flight on its own stream, and the loop polls them, so a family of small
+    grids is never held back by a family of large ones; when a family's
+    macro-iteration completes its finished requests retire at once and the
+    family is relaunched with whoever has joined it meanwhile.
+
+    macro_steps caps the RK steps per instance in one macro-iteration; with
+    macro_updates set, a family takes ceil(macro_updates / its total nodes)
+    steps (at least 1, at most macro_steps), rounded down to a power of two
+    (few distinct step counts, so few distinct captured launch graphs), so a
+    macro-iteration costs about the same device time whatever the family's
+    size.
+    """
 
     def __init__(self, backend, hbm_budget: int, max_active: int = 256, macro_steps: int = 32,
+                 macro_updates: Optional[float] = None, poll_s: float = 2e-4,
                  clock=time.perf_counter, sleep=time.sleep):
         self.backend = backend
         self.hbm_budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.macro_steps = int(macro_steps)
+        self.macro_updates = macro_updates
+        self.poll_s = float(poll_s)
         self.clock = clock
         self.sleep = sleep
+
+    def steps_for(self, group: List[Job]) -> int:
+        if not self.macro_updates:
+            return self.macro_steps
+        pts = sum(j.problem.points for j in group)
+        k = max(1, min(self.macro_steps, int(math.ceil(self.macro_updates / max(pts, 1)))))
+        return 1 << (k.bit_length() - 1)
 
     def run(self, requests: Sequence[inputs.Request], keep_results: bool = False
             ) -> Tuple[ServeReport, List[Job]]:
         jobs = [Job(k, r.problem, r.arrival, t=r.problem.t0) for k, r in enumerate(requests)]
         pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.rid)))
         active: Dict[Tuple, List[Job]] = collections.OrderedDict()
+        inflight = set()
         used = 0
         n_active = 0
         max_active = peak = iters = 0
@@ -140,20 +167,10 @@ class Server:
                 active.setdefault(j.key, []).append(j)
             max_active = max(max_active, n_active)
             peak = max(peak, used)
-            if not n_active:
-                if pending:
-                    wait = pending[0].arrival - (self.clock() - start)
-                    if wait > 0:
-                        self.sleep(min(wait, 0.05))
-                continue
-            # one macro-iteration: every family advances, on its own stream
-            for key, group in active.items():
-                self.backend.advance(key, group, self.macro_steps)
+            # families with nothing in flight: retire, then relaunch
             for key in list(active):
-                self.backend.sync(key)
-            iters += 1
-            done_at = self.clock() - start
-            for key in list(active):
+                if key in inflight:
+                    continue
                 group = active[key]
                 keep = []
                 for j in group:
@@ -163,24 +180,44 @@ class Server:
                         updates += float(j.problem.points) * j.steps_done
                         self.backend.release(j)
                         j.state = "done"
-                        j.finished_at = done_at
+                        j.finished_at = self.clock() - start
                         used -= j.nbytes
                         n_active -= 1
                     else:
                         keep.append(j)
-                if keep:
-                    active[key] = keep
-                else:
+                if not keep:
                     del active[key]
                     self.backend.idle(key)
+                    continue
+                active[key] = keep
+                self.backend.advance(key, keep, self.steps_for(keep))
+                inflight.add(key)
+            if not inflight:
+                if pending and not n_active:
+                    wait = pending[0].arrival - (self.clock() - start)
+                    if wait > 0:
+                        self.sleep(min(wait, 0.05))
+                continue
+            done = [k for k in inflight if self.backend.ready(k)]
+            if not done:
+                self.sleep(self.poll_s)
+                continue
+            for k in done:
+                inflight.discard(k)
+                iters += 1
         makespan = self.clock() - start
         return report(jobs, makespan, max_active, peak, iters, updates), jobs
 
 
 class GpuBackend:
-    """libhj through its C ABI; torch supplies device memory and streams."""
+    """libhj through its C ABI; torch supplies device memory and streams.
 
-    def __init__(self, prec: str = "fp32", tile_nodes: int = 4096, workgroups: int = 1024,
+    Every family has its own stream and engine; uploads of admitted requests
+    go through a separate stream, so admitting never waits for a family's
+    work in flight, and a family's next launch waits on the uploads of the
+    requests that joined it (stream-ordered events, no host wait)."""
+
+    def __init__(self, prec: str = "fp32", tile_nodes: int = 256, workgroups: int = 0,
                  use_graph: bool = True, v0_cache: Optional[Dict[int, np.ndarray]] = None):
         import torch
 
@@ -195,7 +232,9 @@ class GpuBackend:
         self.v0_cache = v0_cache if v0_cache is not None else {}
         self.engines: Dict[Tuple, object] = {}
         self.streams: Dict[Tuple, object] = {}
+        self.events: Dict[Tuple, object] = {}
         self.device = torch.device("cuda")
+        self.upload = torch.cuda.Stream(device=self.device)
 
     def bytes_needed(self, j: Job) -> int:
         # V0, V and two stage buffers, plus the coordinate tables (FP64 and FP32)
@@ -211,42 +250,57 @@ class GpuBackend:
     def admit(self, j: Job):
         torch = self.torch
         p = j.problem
-        _, stream = self._engine(j.key)
         v0h = self.v0_cache.get(j.rid)
         if v0h is None:
             v0h = p.v0()
         try:
-            with torch.cuda.stream(stream):
+            with torch.cuda.stream(self.upload):
                 v0 = torch.from_numpy(np.ascontiguousarray(v0h)).to(self.device, self.dtype,
                                                                      non_blocking=False)
                 v = v0.clone()
                 a = torch.empty_like(v0)
                 b = torch.empty_like(v0)
+                ready = torch.cuda.Event()
+                ready.record(self.upload)
         except RuntimeError as e:  # torch reports device OOM as RuntimeError
             raise MemoryError(str(e))
         g = self.hj.Grid.from_problem(p, self.prec)
         g.set_workspace(a, b)
-        j.dev = {"grid": g, "v0": v0, "v": v}
+        j.dev = {"grid": g, "v0": v0, "v": v, "a": a, "b": b, "ready": ready}
         j.t = p.t0
         j.dev_finished = p.tf <= p.t0
 
     def advance(self, key, group: List[Job], max_steps: int):
         eng, stream = self._engine(key)
         todo = [j for j in group if not j.dev_finished]
-        if not todo:
-            return
-        ts, taken, fin = eng.step([j.dev["grid"] for j in todo], [j.dev["v0"] for j in todo],
-                                  [j.dev["v"] for j in todo], [j.problem.t0 for j in todo],
-                                  [j.t for j in todo], [j.problem.tf for j in todo],
-                                  [j.problem.mode for j in todo], max_steps, stream)
-        for j, t, k, f in zip(todo, ts, taken, fin):
-            j.t = t
-            j.steps_done += k
-            j.dev_finished = f
+        for j in todo:
+            ev = j.dev.pop("ready", None)
+            if ev is not None:  # first launch of a joined request: wait for its upload
+                stream.wait_event(ev)
+                for name in ("v0", "v", "a", "b"):
+                    j.dev[name].record_stream(stream)
+        if todo:
+            ts, taken, fin = eng.step([j.dev["grid"] for j in todo],
+                                      [j.dev["v0"] for j in todo], [j.dev["v"] for j in todo],
+                                      [j.problem.t0 for j in todo], [j.t for j in todo],
+                                      [j.problem.tf for j in todo],
+                                      [j.problem.mode for j in todo], max_steps, stream)
+            for j, t, k, f in zip(todo, ts, taken, fin):
+                j.t = t
+                j.steps_done += k
+                j.dev_finished = f
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        self.events[key] = ev
+
+    def ready(self, key) -> bool:
+        ev = self.events.get(key)
+        return ev is None or ev.query()
 
     def sync(self, key):
-        eng, stream = self._engine(key)
-        stream.synchronize()
+        ev = self.events.get(key)
+        if ev is not None:
+            ev.synchronize()
 
     def idle(self, key):
         pass
@@ -259,6 +313,8 @@ class GpuBackend:
         j.dev = None
 
     def close(self):
+        for key in list(self.events):
+            self.sync(key)
         for e in self.engines.values():
             e.close()
         self.engines.clear()

@@ -57,12 +57,19 @@ def _run_batch(problems, prec, batch=None, **cfg):
     return [o.cpu().numpy().astype(np.float64) for o in outs], tfin, items
 
 
+# launch shapes: flat graph, flat direct, strided graph
+SHAPES = [dict(tile_nodes=256, workgroups=0, use_graph=True),
+          dict(tile_nodes=256, workgroups=0, use_graph=False),
+          dict(tile_nodes=1024, workgroups=512, use_graph=True)]
+
+
+@pytest.mark.parametrize("shape", range(len(SHAPES)))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_equals_plain_bitwise(prec):
+def test_batch_equals_plain_bitwise(prec, shape):
     from gpu_util import gpu_solve
 
     probs = _uneven_rel_dubins(9, seed=1)
-    got, tfin, items = _run_batch(probs, prec, tile_nodes=1024, workgroups=512)
+    got, tfin, items = _run_batch(probs, prec, **SHAPES[shape])
     assert items > 0
     for p, g, t in zip(probs, got, tfin):
         ref = gpu_solve(p, prec)
@@ -100,6 +107,33 @@ def test_batch_graph_replay_new_composition():
         assert np.array_equal(x, y)
 
 
+def test_flat_graph_reuse_and_recapture():
+    """Flat launches from the handle's captured graphs: a batch led by a long
+    instance A (capture), A alone (same round count, fewer workgroups per
+    round: replays that graph, whose extra workgroups return at once), A with
+    wider companions (round 0 needs more workgroups: a new capture), then a
+    small unrelated batch; each equals direct launches."""
+    from paper_2507_11542_amd import hj
+
+    a = inputs.rel_dubins_3d((21, 21, 21), tf=0.3)
+    wide = [a, inputs.rel_dubins_3d((33, 33, 33), tf=0.15),
+            inputs.rel_dubins_3d((41, 41, 41), tf=0.1)]
+    wider = [a, inputs.rel_dubins_3d((41, 41, 41), tf=0.1),
+             inputs.rel_dubins_3d((41, 41, 41), tf=0.12).with_(mode="set"),
+             inputs.rel_dubins_3d((33, 33, 33), tf=0.1)]
+    small = _uneven_rel_dubins(2, seed=5, sizes=(17, 21), horizon=(0.1, 0.2))
+    seq = (wide, [a], wider, small, [a])
+    b = hj.Batch(workgroups=0, use_graph=True)
+    try:
+        got = [_run_batch(ps, "fp32", batch=b)[0] for ps in seq]
+    finally:
+        b.close()
+    for ps, g in zip(seq, got):
+        ref, _, _ = _run_batch(ps, "fp32", workgroups=0, use_graph=False)
+        for x, y in zip(g, ref):
+            assert np.array_equal(x, y)
+
+
 def test_batch_other_dynamics_and_rk2(orc):
     """4-D Dubins (set) and double-integrator ENO2/RK2 batches against the oracle."""
     from gpu_util import oracle_solve
@@ -108,8 +142,8 @@ def test_batch_other_dynamics_and_rk2(orc):
           inputs.dubins4d(n=(15, 11, 10, 9), a_max=1.3, tf=0.5)]
     di = [inputs.double_integrator_2d(n=51, u_max=0.8, tf=0.5),
           inputs.double_integrator_2d(n=77, tf=1.0)]
-    for probs in (d4, di):
-        got, _, _ = _run_batch(probs, "fp64", tile_nodes=512, workgroups=128)
+    for probs, shape in ((d4, SHAPES[0]), (di, SHAPES[0]), (d4, SHAPES[2]), (di, SHAPES[2])):
+        got, _, _ = _run_batch(probs, "fp64", **shape)
         for p, g in zip(probs, got):
             ref, *_ = oracle_solve(orc, p)
             assert np.abs(g - ref).max() <= 1e-12

@@ -23,13 +23,14 @@ def _stream(count=15, seed=5):
                                  rd_sizes=(21, 29), d4_sizes=(11, 15), horizon=(0.1, 0.4))
 
 
+@pytest.mark.parametrize("shape", [(256, 0), (1024, 256)])  # flat, strided
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_served_equals_alone(prec):
+def test_served_equals_alone(prec, shape):
     from gpu_util import gpu_solve
     from paper_2507_11542_amd.serve import GpuBackend, Server
 
     reqs = _stream()
-    be = GpuBackend(prec=prec, tile_nodes=1024, workgroups=256)
+    be = GpuBackend(prec=prec, tile_nodes=shape[0], workgroups=shape[1])
     try:
         rep, jobs = Server(be, hbm_budget=1 << 30, macro_steps=7).run(reqs, keep_results=True)
     finally:

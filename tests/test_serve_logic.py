@@ -21,15 +21,18 @@ class FakeClock:
 
 
 class FakeBackend:
-    """Each macro-iteration costs 1 ms of fake time; a request needs
-    ceil(tf / 0.1) steps."""
+    """A macro-iteration of a family costs `cost(key)` of fake time (1 ms
+    unless given); a request needs ceil(tf / 0.1) steps."""
 
-    def __init__(self, clock, fail_names=()):
+    def __init__(self, clock, fail_names=(), cost=None):
         self.clock = clock
         self.fail_names = set(fail_names)
+        self.cost = cost or (lambda key: 0.001)
         self.live = 0
         self.max_live = 0
         self.released = []
+        self.busy_until = {}
+        self.launches = []
 
     def bytes_needed(self, j):
         return j.problem.points * 16
@@ -43,14 +46,17 @@ class FakeBackend:
         self.max_live = max(self.max_live, self.live)
 
     def advance(self, key, group, k):
+        assert self.ready(key), "relaunched a family still in flight"
+        self.launches.append((key, len(group), k))
         for j in group:
             n = min(k, j.dev["left"])
             j.dev["left"] -= n
             j.steps_done += n
             j.dev_finished = j.dev["left"] == 0
+        self.busy_until[key] = self.clock.t + self.cost(key)
 
-    def sync(self, key):
-        self.clock.t += 0.001
+    def ready(self, key):
+        return self.clock.t >= self.busy_until.get(key, 0.0) - 1e-12
 
     def idle(self, key):
         pass
@@ -125,3 +131,42 @@ def test_idle_waits_for_arrivals():
     assert rep.completed == 2
     assert jobs[0].admitted_at >= 0.5 and jobs[1].admitted_at >= 1.25
     assert rep.makespan_s >= 1.25
+
+
+def _req_dyn(arrival, tf, dyn):
+    if dyn == "d4":
+        p = inputs.dubins4d(n=(9, 9, 9, 9), tf=tf)
+    else:
+        p = inputs.double_integrator_2d(n=21, tf=tf)
+    return inputs.Request(arrival, p)
+
+
+def test_families_progress_independently():
+    """A slow family (4-D, 20 ms per macro-iteration) and a fast one (2-D,
+    1 ms): the 2-D requests finish long before the first 4-D macro-iteration
+    ends, instead of waiting for it at every iteration."""
+    clk = FakeClock()
+    be = FakeBackend(clk, cost=lambda key: 0.020 if key[0] == 4 else 0.001)
+    reqs = [_req_dyn(0.0, 0.9, "d4")] + [_req_dyn(0.0, 0.3, "di") for _ in range(3)]
+    rep, jobs = Server(be, hbm_budget=10 ** 9, macro_steps=2, clock=clk, sleep=clk.sleep).run(reqs)
+    assert rep.completed == 4
+    # di: 3 steps at 2 per iteration = 2 iterations of 1 ms
+    assert all(j.finished_at <= 0.0025 for j in jobs[1:])
+    # d4: 9 steps = 5 iterations of 20 ms
+    assert jobs[0].finished_at == pytest.approx(0.100, abs=1e-3)
+
+
+def test_joiners_wait_for_the_family_in_flight():
+    """A request arriving while its family is in flight joins at the family's
+    next launch, not before; and macro_updates sizes the step count by the
+    family's total nodes."""
+    clk = FakeClock()
+    be = FakeBackend(clk, cost=lambda key: 0.010)
+    reqs = [_req(0.0, 11, 2.0), _req(0.003, 11, 0.2)]
+    srv = Server(be, hbm_budget=10 ** 9, macro_steps=8, macro_updates=4 * 11 ** 3, clock=clk,
+                 sleep=clk.sleep)
+    rep, jobs = srv.run(reqs)
+    assert rep.completed == 2
+    assert be.launches[0] == (jobs[0].key, 1, 4)   # 4 steps for one 11^3 grid
+    assert be.launches[1] == (jobs[0].key, 2, 2)   # joined at 10 ms: 2 steps each
+    assert jobs[1].finished_at == pytest.approx(0.020, abs=1e-3)
