@@ -13,6 +13,8 @@ Functions and the paper passages they follow:
 - ``rhs_at``    L(V) = -Hhat at chosen nodes          (Sec. 4 Lax-Friedrichs)
 - ``steps``     fixed-size TVD-RK steps               (Sec. 5 odeCFL listing)
 - ``solve``     full CFL-constrained solve over tspan (Sec. 5, Sec. 6.1 tube)
+- ``solve_outputs`` the same through a list of output times (Sec. 6.1, the
+                global steps of the rockets game)
 
 Every function is pinned by a ``-m "not gpu"`` test against closed forms,
 invariants, polynomial reproduction, convergence order or brute force; the
@@ -36,8 +38,8 @@ _LIB = os.environ.get("HJ_ORACLE_LIB", _LIB)
 
 SCHEMES = {"upwind1": 1, "eno2": 2, "weno5": 5}
 DYNAMICS = {"translation": 0, "ball": 1, "double_integrator": 2,
-            "rel_dubins": 3, "dubins4d": 4}
-MODES = {"set": 0, "tube": 1}
+            "rel_dubins": 3, "dubins4d": 4, "rockets": 5}
+MODES = {"set": 0, "tube": 1, "tube_vi": 2, "tube_out": 3}
 
 _lib = None
 
@@ -74,6 +76,8 @@ def _load():
     lib.orc_steps.restype = I
     lib.orc_solve.argtypes = [I, P, P, P, U, I, P, I, I, I, D, P, P, D, D, I, P, P]
     lib.orc_solve.restype = L
+    lib.orc_solve_outputs.argtypes = [I, P, P, P, U, I, P, I, I, I, D, P, D, P, L, I, P]
+    lib.orc_solve_outputs.restype = L
     lib.orc_set_threads.argtypes = [I]
     lib.orc_set_threads.restype = I
     _lib = lib
@@ -192,3 +196,25 @@ def solve(v0, n, lo, hi, periodic, dynamics, params, scheme="weno5", order=3,
     if k < 0:
         raise RuntimeError("oracle solve failed (%d)" % k)
     return out, alpha[: len(n)].copy(), float(dt[0]), int(k)
+
+
+def solve_outputs(v0, n, lo, hi, periodic, dynamics, params, times, scheme="weno5",
+                  order=3, cfl=0.8, t0=0.0, mode="set"):
+    """Solve from V0 at t0 through the ascending output times; returns
+    (stack of V at each output time, total step count) (Sec. 5, Sec. 6.1)."""
+    lib = _load()
+    n, lo, hi, mask = _grid_args(n, lo, hi, periodic)
+    p, npar = _params(params)
+    v0 = np.ascontiguousarray(v0, dtype=np.float64)
+    assert v0.size == int(np.prod(n))
+    times = np.ascontiguousarray(times, dtype=np.float64)
+    assert times.ndim == 1 and (times.size == 0 or (times[0] >= t0 and
+                                                    np.all(np.diff(times) >= 0)))
+    outs = np.empty((times.size,) + tuple(int(k) for k in n), dtype=np.float64)
+    k = lib.orc_solve_outputs(len(n), _ptr(n), _ptr(lo), _ptr(hi), mask, DYNAMICS[dynamics],
+                              _ptr(p), npar, SCHEMES[scheme], int(order), float(cfl),
+                              _ptr(v0), float(t0), _ptr(times), int(times.size), MODES[mode],
+                              _ptr(outs))
+    if k < 0:
+        raise RuntimeError("oracle solve failed (%d)" % k)
+    return outs, int(k)

@@ -18,6 +18,10 @@
  *   - dissipation alpha_i = max over nodes of |dH/dp_i| bound, CFL dt [Sec. 4]
  *   - TVD Runge-Kutta 1/2/3 and the CFL time loop        [Sec. 5, odeCFL3 listing]
  *   - tube update V <- min(V, V0) after each step        [Sec. 6.1 BRT]
+ *   - tube as the variational inequality: the update of every stage
+ *     restricted to non-increasing values                [Sec. 6.1, the min[0,H] form]
+ *   - tube update at output times only, output times    [Sec. 6.1, the global steps]
+ *   - the rockets launch game (x, z, theta)              [Sec. 6.1, eq. ham_def]
  *
  * Readings where the paper is silent or garbled (all are also listed in the
  * design notes):
@@ -41,6 +45,21 @@
  *   R12 non-periodic ghosts: linear extrapolation v_{-k} = v_0 + k (v_0 - v_1).
  *   R14 non-periodic axis: dx = (hi-lo)/(N-1), both ends are nodes;
  *       periodic axis: dx = (hi-lo)/N, hi is not a node.
+ *   R20 rockets: the vector field is the one inside the Hamiltonian's
+ *       definition, f = (a cos th + ue x, a sin th + a + up x - g, up - ue)
+ *       with a_p = a_e = a and |ue|, |up| <= umax, the evader maximising
+ *       and the pursuer minimising, so
+ *       H = -a p1 cos th - p2 (a sin th + a - g) - umax |p1 x - p3|
+ *           + umax |p2 x + p3|;
+ *       the relative equations of motion print ue x in zdot and the closed
+ *       form printed after the definition has other signs, so neither is used.
+ *   R21 variational-inequality tube (the min[0,H] form): with V_t + H = 0
+ *       integrated forward, the zero sublevel set may only grow, so every
+ *       stage uses L = min(-Hhat, 0) (V never increases); no min with V0.
+ *   R22 output times: an output time is hit exactly; each interval
+ *       [t_{k-1}, t_k] runs the loop of R6 on its own (rule relative to the
+ *       interval).  The tube-at-outputs mode takes V <- min(V, V0) at the
+ *       output times only.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -55,8 +74,8 @@
  * names to them; nothing outside this file shares them) */
 enum { ORC_UPWIND1 = 1, ORC_ENO2 = 2, ORC_WENO5 = 5 };
 enum { ORC_TRANSLATION = 0, ORC_BALL = 1, ORC_DOUBLE_INTEGRATOR = 2,
-       ORC_REL_DUBINS = 3, ORC_DUBINS4D = 4 };
-enum { ORC_SET = 0, ORC_TUBE = 1 };
+       ORC_REL_DUBINS = 3, ORC_DUBINS4D = 4, ORC_ROCKETS = 5 };
+enum { ORC_SET = 0, ORC_TUBE = 1, ORC_TUBE_VI = 2, ORC_TUBE_OUT = 3 };
 
 typedef struct {
     int nd;
@@ -297,6 +316,10 @@ static void derivs_at(const ogrid *g, const double *v, long node, int d,
  *  DUBINS4D     (x, y, th, v): xdot = v cos th, ydot = v sin th, thdot = w,
  *               vdot = a; control minimises:
  *               H = -p1 v cos th - p2 v sin th + wmax |p3| + amax |p4|
+ *  ROCKETS      (x, z, th), reading R20: p.f = p1 a cos th
+ *               + p2 (a sin th + a - g) + ue (p1 x - p3) + up (p2 x + p3);
+ *               the evader's max gives umax |p1 x - p3|, the pursuer's min
+ *               -umax |p2 x + p3|, and H = -(max min p.f)
  */
 static double hamiltonian(const ogrid *g, const odyn *dy, long node, const double *p)
 {
@@ -331,6 +354,15 @@ static double hamiltonian(const ogrid *g, const odyn *dy, long node, const doubl
         return -p[0] * (v * g->cs[2][k]) - p[1] * (v * g->sn[2][k])
                + wm * fabs(p[2]) + am * fabs(p[3]);
     }
+    case ORC_ROCKETS: {
+        double a = dy->prm[0], grav = dy->prm[1], um = dy->prm[2];
+        double x = g->x[0][axis_index(g, node, 0)];
+        long k = axis_index(g, node, 2);
+        double drift1 = a * g->cs[2][k];
+        double drift2 = a * g->sn[2][k] + a - grav;
+        return -p[0] * drift1 - p[1] * drift2 - um * fabs(p[0] * x - p[2])
+               + um * fabs(p[1] * x + p[2]);
+    }
     }
     return 0.0;
 }
@@ -363,6 +395,16 @@ static double speed_bound(const ogrid *g, const odyn *dy, long node, int d)
         if (d == 1) return fabs(v * g->sn[2][k]);
         if (d == 2) return dy->prm[0];
         return dy->prm[1];
+    }
+    case ORC_ROCKETS: {
+        /* |f1| <= |a cos th| + umax |x|, |f2| <= |a sin th + a - g| + umax |x|,
+         * |f3| <= 2 umax */
+        double a = dy->prm[0], grav = dy->prm[1], um = dy->prm[2];
+        double x = g->x[0][axis_index(g, node, 0)];
+        long k = axis_index(g, node, 2);
+        if (d == 0) return fabs(a * g->cs[2][k]) + um * fabs(x);
+        if (d == 1) return fabs(a * g->sn[2][k] + a - grav) + um * fabs(x);
+        return 2.0 * um;
     }
     }
     return 0.0;
@@ -409,12 +451,17 @@ static double rhs_at(const ogrid *g, const odyn *dy, int scheme,
     return -hhat;
 }
 
+/* L(V) at every node; in the variational-inequality tube (reading R21) the
+ * update is restricted to L <= 0. */
 static void rhs_all(const ogrid *g, const odyn *dy, int scheme,
-                    const double *alpha, const double *v, double *out)
+                    const double *alpha, const double *v, double *out, int mode)
 {
 #pragma omp parallel for schedule(static)
-    for (long node = 0; node < g->total; ++node)
-        out[node] = rhs_at(g, dy, scheme, alpha, v, node);
+    for (long node = 0; node < g->total; ++node) {
+        double l = rhs_at(g, dy, scheme, alpha, v, node);
+        if (mode == ORC_TUBE_VI && l > 0.0) l = 0.0;
+        out[node] = l;
+    }
 }
 
 /* Sec. 5 (odeCFL listing) and readings R7, R8, R11: one TVD-RK step of size h
@@ -425,25 +472,25 @@ static void rk_step(const ogrid *g, const odyn *dy, int scheme, int order,
 {
     long n = g->total;
     if (order == 1) {
-        rhs_all(g, dy, scheme, alpha, v, l);
+        rhs_all(g, dy, scheme, alpha, v, l, mode);
         for (long k = 0; k < n; ++k) v[k] = v[k] + h * l[k];
     } else if (order == 2) {
-        rhs_all(g, dy, scheme, alpha, v, l);
+        rhs_all(g, dy, scheme, alpha, v, l, mode);
         for (long k = 0; k < n; ++k) w1[k] = v[k] + h * l[k];
-        rhs_all(g, dy, scheme, alpha, w1, l);
+        rhs_all(g, dy, scheme, alpha, w1, l, mode);
         for (long k = 0; k < n; ++k) {
             double v2 = w1[k] + h * l[k];
             v[k] = (v[k] + v2) / 2.0;
         }
     } else {
-        rhs_all(g, dy, scheme, alpha, v, l);
+        rhs_all(g, dy, scheme, alpha, v, l, mode);
         for (long k = 0; k < n; ++k) w1[k] = v[k] + h * l[k];
-        rhs_all(g, dy, scheme, alpha, w1, l);
+        rhs_all(g, dy, scheme, alpha, w1, l, mode);
         for (long k = 0; k < n; ++k) {
             double v2 = w1[k] + h * l[k];
             w2[k] = (3.0 * v[k] + v2) / 4.0;
         }
-        rhs_all(g, dy, scheme, alpha, w2, l);
+        rhs_all(g, dy, scheme, alpha, w2, l, mode);
         for (long k = 0; k < n; ++k) {
             double v3 = w2[k] + h * l[k];
             v[k] = (v[k] + 2.0 * v3) / 3.0;
@@ -610,6 +657,71 @@ long orc_solve(int nd, const long *n, const double *lo, const double *hi,
             ++steps;
         }
     }
+    if (mode == ORC_TUBE_OUT) /* reading R22: the one output time is tf */
+        for (long q = 0; q < g.total; ++q)
+            if (v0[q] < v_out[q]) v_out[q] = v0[q];
+    free(w1);
+    free(w2);
+    free(l);
+    grid_free(&g);
+    return steps;
+}
+
+/* Solve from V0 at t0 through the output times times[0..ntimes) (ascending,
+ * times[0] >= t0), writing V at each into v_outs[k * total ...] (readings
+ * R22 and R11/R21; in the tube-at-outputs mode V <- min(V, V0) is taken at
+ * each output time only).  Returns the total step count or a negative code. */
+long orc_solve_outputs(int nd, const long *n, const double *lo, const double *hi,
+                       unsigned pmask, int dyn, const double *prm, int nprm,
+                       int scheme, int order, double cfl, const double *v0,
+                       double t0, const double *times, long ntimes, int mode,
+                       double *v_outs)
+{
+    ogrid g;
+    odyn dy;
+    memset(&g, 0, sizeof(g));
+    if (setup(&g, &dy, nd, n, lo, hi, pmask, dyn, prm, nprm) != 0) {
+        grid_free(&g);
+        return -1;
+    }
+    double alpha[ORC_MAXD] = {0, 0, 0, 0};
+    compute_alpha(&g, &dy, alpha);
+    double dt = cfl_dt(&g, alpha, cfl);
+    size_t bytes = sizeof(double) * (size_t)g.total;
+    double *v = (double *)malloc(bytes);
+    double *w1 = (double *)malloc(bytes), *w2 = (double *)malloc(bytes),
+           *l = (double *)malloc(bytes);
+    if (!v || !w1 || !w2 || !l) {
+        free(v);
+        free(w1);
+        free(w2);
+        free(l);
+        grid_free(&g);
+        return -2;
+    }
+    memcpy(v, v0, bytes);
+    /* the per-step update: none in the tube-at-outputs mode */
+    const int step_mode = mode == ORC_TUBE_OUT ? ORC_SET : mode;
+    const double eps = 100.0 * 2.220446049250313e-16;
+    long steps = 0;
+    double t = t0;
+    for (long k = 0; k < ntimes; ++k) {
+        double ta = t, tb = times[k];
+        if (tb > ta) {
+            while (tb - t >= eps * (tb - ta)) {
+                double h = dt < tb - t ? dt : tb - t;
+                rk_step(&g, &dy, scheme, order, alpha, h, v, v0, step_mode, w1, w2, l);
+                t = t + h;
+                ++steps;
+            }
+        }
+        t = tb;
+        if (mode == ORC_TUBE_OUT)
+            for (long q = 0; q < g.total; ++q)
+                if (v0[q] < v[q]) v[q] = v0[q];
+        memcpy(v_outs + (size_t)k * (size_t)g.total, v, bytes);
+    }
+    free(v);
     free(w1);
     free(w2);
     free(l);

@@ -17,6 +17,11 @@ Workloads (the analytic problems the solver is measured on):
 - ``dubins4d``: 4-D Dubins car with speed state, 61^4 on
   [-5,5]^2 x [-pi,pi) x [0,4] (theta periodic), V0 = sqrt(x^2+y^2) - 1,
   WENO5 / LF / TVD-RK3, reachable set to t = 2.
+- ``rockets``: the rockets launch game of Dreyfus in relative coordinates
+  (x, z, theta), a = 1, g = 32, |u| <= 1, 100^3 on [-64,64]^2 x
+  [-pi/2, pi/2] (no periodic axis), V0 = sqrt(x^2+z^2) - 1.5 (the capture
+  circle, a cylinder along theta), ENO2 / LF / TVD-RK3, tube as the
+  variational inequality over t in [-2.5, 0] with 11 output times.
 - ``serving_stream``: Poisson arrivals mixing the three families.
 """
 from __future__ import annotations
@@ -140,6 +145,19 @@ def dubins4d(n=61, w_max=1.0, a_max=1.0, tf=2.0, scheme="weno5", order=3) -> Pro
                    (5.0, 5.0, math.pi, 4.0), (False, False, True, False), "dubins4d",
                    (w_max, a_max), scheme=scheme, order=order, cfl=0.8, tf=tf,
                    mode="set", radius=1.0)
+
+
+def rockets(n=100, a=1.0, g=32.0, u_max=1.0, t0=-2.5, tf=0.0, scheme="eno2", order=3,
+            mode="tube_vi") -> Problem:
+    n3 = (n, n, n) if np.isscalar(n) else tuple(n)
+    return Problem("rockets", n3, (-64.0, -64.0, -math.pi / 2), (64.0, 64.0, math.pi / 2),
+                   (False, False, False), "rockets", (a, g, u_max), scheme=scheme,
+                   order=order, cfl=0.8, t0=t0, tf=tf, mode=mode, radius=1.5)
+
+
+def output_times(t0: float, tf: float, count: int = 11) -> np.ndarray:
+    """count equally spaced output times from t0 to tf (both included)."""
+    return np.linspace(t0, tf, count)
 
 
 def rel_dubins_batch(count=64, seed=0, sizes=(51, 61, 81, 101)) -> List[Problem]:

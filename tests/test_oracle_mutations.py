@@ -46,7 +46,20 @@ MUTATIONS = {
                                 "if (d == 0) return dy->prm[0];"),
     "cfl_rate": ("rate += alpha[d] / g->dx[d];", "rate += alpha[d] * g->dx[d];"),
     "periodic_cell_size": ("(hi[d] - lo[d]) / (double)n[d]", "(hi[d] - lo[d]) / (double)(n[d] - 1)"),
+    "rockets_evader_abs_argument": ("- um * fabs(p[0] * x - p[2])", "- um * fabs(p[0] * x + p[2])"),
+    "rockets_pursuer_sign": ("+ um * fabs(p[1] * x + p[2]);", "- um * fabs(p[1] * x + p[2]);"),
+    "rockets_gravity_sign": ("double drift2 = a * g->sn[2][k] + a - grav;",
+                             "double drift2 = a * g->sn[2][k] + a + grav;"),
+    "rockets_alpha_misses_x": ("if (d == 0) return fabs(a * g->cs[2][k]) + um * fabs(x);",
+                               "if (d == 0) return fabs(a * g->cs[2][k]);"),
+    "vi_restricts_the_wrong_way": ("if (mode == ORC_TUBE_VI && l > 0.0) l = 0.0;",
+                                   "if (mode == ORC_TUBE_VI && l < 0.0) l = 0.0;"),
+    "vi_restricts_nothing": ("if (mode == ORC_TUBE_VI && l > 0.0) l = 0.0;", ""),
+    "tube_out_every_step": ("const int step_mode = mode == ORC_TUBE_OUT ? ORC_SET : mode;",
+                            "const int step_mode = mode == ORC_TUBE_OUT ? ORC_TUBE : mode;"),
 }
+
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_rockets_tubes.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -60,7 +73,7 @@ def test_pins_catch_mutation(name, tmp_path):
     subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
                     "-std=c99", "-o", str(lib), str(mut), "-lm"], check=True)
     env = dict(os.environ, HJ_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] +
+                       [os.path.join(ROOT, "tests", f) for f in PIN_FILES],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "mutation %s survived the pins:\n%s" % (name, r.stdout[-2000:])
