@@ -51,8 +51,13 @@ typedef enum {
 typedef enum { HJ_FP64 = 0, HJ_FP32 = 1 } hj_precision;
 
 /* HJ_SET: the reachable set V(tf).  HJ_TUBE: the tube, V <- min(V, V0) after
- * every full step (Sec. 6.1, backward reachable tube). */
-typedef enum { HJ_SET = 0, HJ_TUBE = 1 } hj_mode;
+ * every full step (Sec. 6.1, backward reachable tube).  HJ_TUBE_VI: the tube
+ * as the variational inequality of Sec. 6.1 (its min[0, H] form): every RK
+ * stage uses L = min(L, 0), so V never increases and the zero sublevel set
+ * only grows; V0 is not read after the start.  HJ_TUBE_OUTPUTS: V <- min(V, V0)
+ * at the output times only (hj_solve: at tf; hj_solve_outputs: at each
+ * output time), free steps in between. */
+typedef enum { HJ_SET = 0, HJ_TUBE = 1, HJ_TUBE_VI = 2, HJ_TUBE_OUTPUTS = 3 } hj_mode;
 
 /* One-sided derivative approximations (Sec. 3): first order (Sec. 3.1, halo
  * 1), ENO2 (Sec. 3.2, halo 2), WENO5 (Sec. 3.3, halo 3). */
@@ -71,13 +76,21 @@ typedef enum { HJ_RK1 = 1, HJ_RK2 = 2, HJ_RK3 = 3 } hj_time;
  *                                       pursuit-evasion; evader (|we|) maximises,
  *                                       pursuer (|wp|) minimises
  *   HJ_DYN_DUBINS4D          ndim 4     wmax, amax          (x, y, th, v) Dubins car with
- *                                       speed state, control minimises */
+ *                                       speed state, control minimises
+ *   HJ_DYN_ROCKETS           ndim 3     a, g, umax          (x, z, th) rockets launch game
+ *                                       of Sec. 6.1 with the vector field of eq. ham_def,
+ *                                       x' = a cos th + ue x, z' = a sin th + a + up x - g,
+ *                                       th' = up - ue, |ue|,|up| <= umax, evader (ue)
+ *                                       maximises, pursuer (up) minimises:
+ *                                       H = -a p1 cos th - p2 (a sin th + a - g)
+ *                                           - umax|p1 x - p3| + umax|p2 x + p3| */
 typedef enum {
     HJ_DYN_TRANSLATION = 0,
     HJ_DYN_BALL = 1,
     HJ_DYN_DOUBLE_INTEGRATOR = 2,
     HJ_DYN_REL_DUBINS = 3,
-    HJ_DYN_DUBINS4D = 4
+    HJ_DYN_DUBINS4D = 4,
+    HJ_DYN_ROCKETS = 5
 } hj_dyn;
 
 /* Sec. 2.1 (createGrid(min, max, N, pdim)).  ndim in [1, 4]; N[i] nodes on
@@ -107,20 +120,32 @@ hj_status hj_set_scheme(hj_grid_t g, hj_space space, hj_time time, double cfl);
 hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double tf,
                    hj_mode mode, void *hip_stream);
 
+/* Sec. 6.1 (the global time steps of the rockets game) with the Sec. 5 loop:
+ * a solve from V0 at t0 through the output times times[0..ntimes) (host
+ * array, ascending, times[0] >= t0).  Each interval [t_{k-1}, t_k] runs the
+ * loop of hj_solve on its own and ends exactly at t_k.  V_outs is one device
+ * array of ntimes * prod(N) elements: V(t_k) is written at offset
+ * k * prod(N); it must not overlap V0.  Enqueues on hip_stream after one
+ * synchronisation (alpha).  HJ_E_ARG on NULL pointers, ntimes < 1, times out
+ * of order or before t0, overlap, or non-finite times. */
+hj_status hj_solve_outputs(hj_grid_t g, const void *V0, void *V_outs, double t0,
+                           const double *times, int ntimes, hj_mode mode, void *hip_stream);
+
 /* Precision form of hj_solve for an HJ_FP32 grid: V0 and V_out are FP64
  * device arrays; V0 is rounded to FP32, the whole solve runs in FP32 storage
  * and arithmetic (alpha, dt and t in FP64), and the result is widened to FP64
  * with the tube comparison of Sec. 6.1 taken again in FP64 where the zero
  * level set lies: V_out = min(V32, V0) on the band |V32| <= band (HJ_TUBE),
  * V32 elsewhere.  band < 0 selects 3 max(dx).  The handle keeps two FP32
- * working arrays.  HJ_E_ARG on an FP64 grid or the argument errors of
+ * working arrays.  Modes HJ_SET, HJ_TUBE and HJ_TUBE_VI (no FP64 minimum
+ * for the last).  HJ_E_ARG on an FP64 grid or the argument errors of
  * hj_solve. */
 hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0, double tf,
                          hj_mode mode, double band, void *hip_stream);
 
 /* One full TVD-RK step in place on V (device), of size min(dt, tf - *t),
  * then the tube update against V0 when mode is HJ_TUBE (V0 may be NULL for
- * HJ_SET).  *t advances by the step (FP64, host); *dt_used receives it
+ * HJ_SET and HJ_TUBE_VI; HJ_TUBE_OUTPUTS is not a per-step mode: HJ_E_ARG).  *t advances by the step (FP64, host); *dt_used receives it
  * (may be NULL).  alpha is reduced on the first call and cached.  Resuming a
  * solve from (V, t) is a sequence of hj_step calls. */
 hj_status hj_step(hj_grid_t g, void *V, const void *V0, double *t, double tf,
@@ -173,8 +198,8 @@ hj_status hj_batch_config(hj_batch_t b, int tile_nodes, int workgroups, int use_
  * alpha reduction per instance (one synchronisation for all), then enqueues
  * the uploads and the launch on hip_stream and returns.  A second call waits
  * for the previous one of the same handle to finish before it reuses the
- * tables.  HJ_E_ARG on mismatched or invalid instances, HJ_E_UNSUPPORTED for
- * first-order schemes or RK1. */
+ * tables.  Modes HJ_SET, HJ_TUBE and HJ_TUBE_VI.  HJ_E_ARG on mismatched or
+ * invalid instances, HJ_E_UNSUPPORTED for first-order schemes or RK1. */
 hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
                          void *const *Vouts, const double *t0, const double *tf,
                          const hj_mode *modes, void *hip_stream);

@@ -39,6 +39,14 @@ __device__ inline double speed_bound(const AlphaArgs &a, const int *ii, int d)
         if (d == 0) return fabs(-ve + vp * c) + we * fabs(y);
         if (d == 1) return fabs(vp * s) + we * fabs(x);
         return we + wp;
+    } else if constexpr (DYN == kRockets) {
+        const double am = a.prm[0], grav = a.prm[1], um = a.prm[2];
+        const double x = a.tab[a.tab_off[0] + ii[0]];
+        const double c = a.tab[a.tab_off[2] + a.n[2] + ii[2]];
+        const double s = a.tab[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+        if (d == 0) return fabs(am * c) + um * fabs(x);
+        if (d == 1) return fabs(am * s + am - grav) + um * fabs(x);
+        return 2.0 * um;
     } else {
         const double c = a.tab[a.tab_off[2] + a.n[2] + ii[2]];
         const double s = a.tab[a.tab_off[2] + 2 * a.n[2] + ii[2]];
@@ -159,6 +167,9 @@ hipError_t launch_alpha(int ndim, int dyn, const AlphaArgs &a, double *partial, 
         break;
     case kRelDubins:
         if (ndim == 3) return run<3, kRelDubins>(a, partial, alpha, s);
+        break;
+    case kRockets:
+        if (ndim == 3) return run<3, kRockets>(a, partial, alpha, s);
         break;
     case kDubins4D:
         if (ndim == 4) return run<4, kDubins4D>(a, partial, alpha, s);

@@ -191,10 +191,19 @@ hj_status launch<float>(hj_grid_t g, const StageArgs<float> &a, hipStream_t s)
     return HJ_OK;
 }
 
+// What a step does beyond the free RK stages: the tube minimum with v0 in
+// its last stage, the restricted update L = min(L, 0) in every stage.
+struct StepKind {
+    bool tube;
+    bool vi;
+};
+
+StepKind step_kind(hj_mode mode) { return StepKind{mode == HJ_TUBE, mode == HJ_TUBE_VI}; }
+
 // One stage: out = combine(vs, vb, L(vs)), then min with v0 when tube.
 template <typename T>
 hj_status stage(hj_grid_t g, const void *vs, const void *vb, const void *v0, void *out,
-                Combine c, double dt, double wb, double w2, double den, bool tube,
+                Combine c, double dt, double wb, double w2, double den, bool tube, bool vi,
                 hipStream_t s)
 {
     StageArgs<T> a = base_args<T>(g);
@@ -208,6 +217,7 @@ hj_status stage(hj_grid_t g, const void *vs, const void *vb, const void *v0, voi
     a.w2 = T(w2);
     a.den = T(den);
     a.tube = tube ? 1 : 0;
+    a.vi = vi ? 1 : 0;
     return launch<T>(g, a, s);
 }
 
@@ -215,37 +225,50 @@ hj_status stage(hj_grid_t g, const void *vs, const void *vb, const void *v0, voi
 //   RK1  v <- v + h L(v)
 //   RK2  A <- v + h L(v);  v <- (v + (A + h L(A))) / 2
 //   RK3  A <- v + h L(v);  B <- (3v + (A + h L(A))) / 4;  v <- (v + 2(B + h L(B))) / 3
-// followed by the tube minimum with v0 (fused in the last stage).
+// followed by the tube minimum with v0 (fused in the last stage); every
+// stage restricts its update in the variational-inequality tube.
 template <typename T>
-hj_status rk_step(hj_grid_t g, void *v, const void *v0, bool tube, double h, hipStream_t s)
+hj_status rk_step(hj_grid_t g, void *v, const void *v0, StepKind k, double h, hipStream_t s)
 {
     hj_status st;
     if (g->order == 1) {
-        if ((st = stage<T>(g, v, nullptr, v0, g->bufA, kEuler, h, 0, 0, 1, tube, s)) != HJ_OK)
+        if ((st = stage<T>(g, v, nullptr, v0, g->bufA, kEuler, h, 0, 0, 1, k.tube, k.vi, s)) !=
+            HJ_OK)
             return st;
         HJ_HIP(hipMemcpyAsync(v, g->bufA, g->bytes(), hipMemcpyDeviceToDevice, s),
                "RK1 copy-back");
         return HJ_OK;
     }
-    if ((st = stage<T>(g, v, nullptr, nullptr, g->bufA, kEuler, h, 0, 0, 1, false, s)) != HJ_OK)
-        return st;
-    if (g->order == 2)
-        return stage<T>(g, g->bufA, v, v0, v, kBlend, h, 1.0, 1.0, 2.0, tube, s);
-    if ((st = stage<T>(g, g->bufA, v, nullptr, g->bufB, kBlend, h, 3.0, 1.0, 4.0, false, s)) !=
+    if ((st = stage<T>(g, v, nullptr, nullptr, g->bufA, kEuler, h, 0, 0, 1, false, k.vi, s)) !=
         HJ_OK)
         return st;
-    return stage<T>(g, g->bufB, v, v0, v, kBlend, h, 1.0, 2.0, 3.0, tube, s);
+    if (g->order == 2)
+        return stage<T>(g, g->bufA, v, v0, v, kBlend, h, 1.0, 1.0, 2.0, k.tube, k.vi, s);
+    if ((st = stage<T>(g, g->bufA, v, nullptr, g->bufB, kBlend, h, 3.0, 1.0, 4.0, false, k.vi,
+                       s)) != HJ_OK)
+        return st;
+    return stage<T>(g, g->bufB, v, v0, v, kBlend, h, 1.0, 2.0, 3.0, k.tube, k.vi, s);
 }
 
+// The steps hs in place on v.  In the tube-at-outputs mode the steps are free
+// except the last, whose last stage takes the minimum with v0.
 template <typename T>
-hj_status run_steps(hj_grid_t g, void *v, const void *v0, bool tube,
+hj_status run_steps(hj_grid_t g, void *v, const void *v0, hj_mode mode,
                     const std::vector<double> &hs, hipStream_t s)
 {
-    for (double h : hs) {
-        hj_status st = rk_step<T>(g, v, v0, tube, h, s);
+    const StepKind k = step_kind(mode);
+    for (size_t i = 0; i < hs.size(); ++i) {
+        StepKind ki = k;
+        if (mode == HJ_TUBE_OUTPUTS && i + 1 == hs.size()) ki.tube = true;
+        hj_status st = rk_step<T>(g, v, v0, ki, hs[i], s);
         if (st != HJ_OK) return st;
     }
     return HJ_OK;
+}
+
+bool known_mode(hj_mode m)
+{
+    return m == HJ_SET || m == HJ_TUBE || m == HJ_TUBE_VI || m == HJ_TUBE_OUTPUTS;
 }
 
 bool overlap(const void *a, const void *b, size_t bytes)
@@ -351,6 +374,7 @@ hj_status hj_set_dynamics(hj_grid_t g, hj_dyn kind, const double *params, int np
     case HJ_DYN_DOUBLE_INTEGRATOR: want = 1; nd_need = 2; break;
     case HJ_DYN_REL_DUBINS: want = 4; nd_need = 3; break;
     case HJ_DYN_DUBINS4D: want = 2; nd_need = 4; break;
+    case HJ_DYN_ROCKETS: want = 3; nd_need = 3; break;
     default: return fail(HJ_E_ARG, "unknown dynamics");
     }
     if (nd_need && g->nd != nd_need)
@@ -404,7 +428,7 @@ hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double t
     hj_status s = check_ready(g);
     if (s != HJ_OK) return s;
     if (!V0 || !V_out) return fail(HJ_E_ARG, "V0 and V_out must be non-NULL");
-    if (mode != HJ_SET && mode != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
+    if (!known_mode(mode)) return fail(HJ_E_ARG, "unknown mode");
     if (!(std::isfinite(t0) && std::isfinite(tf) && tf >= t0))
         return fail(HJ_E_ARG, "need finite t0 <= tf");
     if (overlap(V0, V_out, g->bytes())) return fail(HJ_E_ARG, "V_out overlaps V0");
@@ -415,9 +439,47 @@ hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double t
     std::vector<double> hs;
     schedule(cfl_dt(g), t0, tf, &hs);
     HJ_HIP(hipMemcpyAsync(V_out, V0, g->bytes(), hipMemcpyDeviceToDevice, st), "copy V0");
-    const bool tube = mode == HJ_TUBE;
-    if (g->prec == HJ_FP64) return run_steps<double>(g, V_out, V0, tube, hs, st);
-    return run_steps<float>(g, V_out, V0, tube, hs, st);
+    if (g->prec == HJ_FP64) return run_steps<double>(g, V_out, V0, mode, hs, st);
+    return run_steps<float>(g, V_out, V0, mode, hs, st);
+}
+
+hj_status hj_solve_outputs(hj_grid_t g, const void *V0, void *V_outs, double t0,
+                           const double *times, int ntimes, hj_mode mode, void *hip_stream)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (!V0 || !V_outs || !times) return fail(HJ_E_ARG, "V0, V_outs and times must be non-NULL");
+    if (ntimes < 1) return fail(HJ_E_ARG, "need ntimes >= 1");
+    if (!known_mode(mode)) return fail(HJ_E_ARG, "unknown mode");
+    if (!std::isfinite(t0)) return fail(HJ_E_ARG, "non-finite t0");
+    for (int k = 0; k < ntimes; ++k)
+        if (!std::isfinite(times[k]) || times[k] < (k ? times[k - 1] : t0))
+            return fail(HJ_E_ARG, "output times must be finite, ascending and >= t0");
+    const size_t bytes = g->bytes();
+    const uintptr_t a = uintptr_t(V0), b = uintptr_t(V_outs);
+    if (a < b + bytes * size_t(ntimes) && b < a + bytes)
+        return fail(HJ_E_ARG, "V_outs overlaps V0");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = use_device(g)) != HJ_OK) return s;
+    if ((s = ensure_buffers(g, g->order == 3)) != HJ_OK) return s;
+    if ((s = compute_alpha(g, st)) != HJ_OK) return s;
+    const double dt = cfl_dt(g);
+    double t = t0;
+    const void *prev = V0;
+    for (int k = 0; k < ntimes; ++k) {
+        void *out = (char *)V_outs + bytes * size_t(k);
+        HJ_HIP(hipMemcpyAsync(out, prev, bytes, hipMemcpyDeviceToDevice, st), "copy V");
+        std::vector<double> hs;
+        schedule(dt, t, times[k], &hs);  // the interval's own loop
+        if (g->prec == HJ_FP64)
+            s = run_steps<double>(g, out, V0, mode, hs, st);
+        else
+            s = run_steps<float>(g, out, V0, mode, hs, st);
+        if (s != HJ_OK) return s;
+        t = times[k];
+        prev = out;
+    }
+    return HJ_OK;
 }
 
 hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0, double tf,
@@ -427,7 +489,8 @@ hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0
     if (s != HJ_OK) return s;
     if (g->prec != HJ_FP32) return fail(HJ_E_ARG, "hj_solve_mixed needs an HJ_FP32 grid");
     if (!V0 || !V_out) return fail(HJ_E_ARG, "V0 and V_out must be non-NULL");
-    if (mode != HJ_SET && mode != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
+    if (mode != HJ_SET && mode != HJ_TUBE && mode != HJ_TUBE_VI)
+        return fail(HJ_E_ARG, "hj_solve_mixed takes HJ_SET, HJ_TUBE or HJ_TUBE_VI");
     if (!(std::isfinite(t0) && std::isfinite(tf) && tf >= t0))
         return fail(HJ_E_ARG, "need finite t0 <= tf");
     const size_t b64 = size_t(g->total) * sizeof(double);
@@ -456,7 +519,8 @@ hj_status hj_step(hj_grid_t g, void *V, const void *V0, double *t, double tf, hj
     hj_status s = check_ready(g);
     if (s != HJ_OK) return s;
     if (!V || !t) return fail(HJ_E_ARG, "V and t must be non-NULL");
-    if (mode != HJ_SET && mode != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
+    if (mode != HJ_SET && mode != HJ_TUBE && mode != HJ_TUBE_VI)
+        return fail(HJ_E_ARG, "hj_step takes HJ_SET, HJ_TUBE or HJ_TUBE_VI");
     if (mode == HJ_TUBE && !V0) return fail(HJ_E_ARG, "tube mode needs V0");
     if (!(std::isfinite(*t) && std::isfinite(tf))) return fail(HJ_E_ARG, "non-finite time");
     hipStream_t st = (hipStream_t)hip_stream;
@@ -470,9 +534,9 @@ hj_status hj_step(hj_grid_t g, void *V, const void *V0, double *t, double tf, hj
     }
     const double h = dt < tf - *t ? dt : tf - *t;
     if (g->prec == HJ_FP64)
-        s = rk_step<double>(g, V, V0, mode == HJ_TUBE, h, st);
+        s = rk_step<double>(g, V, V0, step_kind(mode), h, st);
     else
-        s = rk_step<float>(g, V, V0, mode == HJ_TUBE, h, st);
+        s = rk_step<float>(g, V, V0, step_kind(mode), h, st);
     if (s != HJ_OK) return s;
     *t = *t + h;
     if (dt_used) *dt_used = h;
@@ -489,8 +553,8 @@ hj_status hj_rhs(hj_grid_t g, const void *V, void *L_out, void *hip_stream)
     if ((s = use_device(g)) != HJ_OK) return s;
     if (!g->alpha_valid && (s = compute_alpha(g, st)) != HJ_OK) return s;
     if (g->prec == HJ_FP64)
-        return stage<double>(g, V, nullptr, nullptr, L_out, kRhs, 0, 0, 0, 1, false, st);
-    return stage<float>(g, V, nullptr, nullptr, L_out, kRhs, 0, 0, 0, 1, false, st);
+        return stage<double>(g, V, nullptr, nullptr, L_out, kRhs, 0, 0, 0, 1, false, false, st);
+    return stage<float>(g, V, nullptr, nullptr, L_out, kRhs, 0, 0, 0, 1, false, false, st);
 }
 
 hj_status hj_grid_set_workspace(hj_grid_t g, void *A, void *B)

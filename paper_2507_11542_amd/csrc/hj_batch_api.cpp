@@ -269,7 +269,7 @@ uint32_t instance_tile(uint32_t total, uint32_t max_tile)
 
 template <typename T>
 void fill_inst(void *dst, hj_grid_t g, void *vout, const void *v0, double dt, double t0,
-               double tf, uint32_t tiles, uint32_t tile_nodes, uint32_t steps, bool tube)
+               double tf, uint32_t tiles, uint32_t tile_nodes, uint32_t steps, hj_mode mode)
 {
     BatchInst<T> in;
     std::memset(&in, 0, sizeof(in));
@@ -284,7 +284,8 @@ void fill_inst(void *dst, hj_grid_t g, void *vout, const void *v0, double dt, do
     in.tiles = tiles;
     in.tile_nodes = tile_nodes;
     in.steps = steps;
-    in.tube = tube ? 1 : 0;
+    in.tube = mode == HJ_TUBE ? 1 : 0;
+    in.vi = mode == HJ_TUBE_VI ? 1 : 0;
     std::memcpy(dst, &in, sizeof(in));
 }
 
@@ -361,7 +362,8 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
             g->order != g0->order || g->prec != g0->prec || g->device != b->device)
             return fail(HJ_E_ARG, "instances must share ndim, dynamics, scheme, RK order, "
                                   "precision and device");
-        if (modes[i] != HJ_SET && modes[i] != HJ_TUBE) return fail(HJ_E_ARG, "unknown mode");
+        if (modes[i] != HJ_SET && modes[i] != HJ_TUBE && modes[i] != HJ_TUBE_VI)
+            return fail(HJ_E_ARG, "batched modes are HJ_SET, HJ_TUBE and HJ_TUBE_VI");
         const void *v0 = V0s ? V0s[i] : nullptr;
         if (!Vs[i] || ((copy_v0 || modes[i] == HJ_TUBE) && !v0))
             return fail(HJ_E_ARG, "NULL V, or NULL V0 where it is read");
@@ -450,14 +452,13 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
     const size_t isz = inst_size(g0->prec);
     for (int i = 0; i < n; ++i) {
         char *dst = (char *)b->h_inst + isz * i;
-        const bool tube = modes[i] == HJ_TUBE;
         const void *v0 = V0s ? V0s[i] : nullptr;
         if (g0->prec == HJ_FP64)
             fill_inst<double>(dst, gs[i], Vs[i], v0, dts[i], tcur[i], tf[i], tiles[i], tsize[i],
-                              steps[i], tube);
+                              steps[i], modes[i]);
         else
             fill_inst<float>(dst, gs[i], Vs[i], v0, dts[i], tcur[i], tf[i], tiles[i], tsize[i],
-                             steps[i], tube);
+                             steps[i], modes[i]);
     }
     std::memset(b->h_gl, 0, sizeof(BatchGlobal));
     b->h_gl->items = uint32_t(total);

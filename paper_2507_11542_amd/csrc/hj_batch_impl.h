@@ -32,7 +32,8 @@ struct BatchInst {
     uint32_t tiles;    // tiles per round
     uint32_t steps;    // RK steps
     uint32_t tile_nodes;  // nodes per tile of this instance
-    int tube;
+    int tube;          // min with v0 after every step
+    int vi;            // restricted update in every stage
 };
 
 struct TileRef {
@@ -89,6 +90,7 @@ __device__ inline StageArgs<T> batch_stage_args(const BatchPtrs<T> &p, uint32_t 
     a.dt = T(h);
     a.v0 = in.v0;
     a.tube = 0;
+    a.vi = in.vi;
     if (stage == 0) {
         a.vs = in.v;
         a.vb = nullptr;
@@ -244,6 +246,9 @@ hipError_t batch_launch_t(int ndim, int space, int dyn, const BatchPtrs<T> &p, u
         break;
     case kDubins4D:
         if (ndim == 4) return batch_launch_space<T, 4, kDubins4D>(space, p, rounds, wg, s);
+        break;
+    case kRockets:
+        if (ndim == 3) return batch_launch_space<T, 3, kRockets>(space, p, rounds, wg, s);
         break;
     }
     return hipErrorInvalidValue;

@@ -10,7 +10,14 @@ namespace hj {
 constexpr int kMaxDim = 4;
 
 enum Space { kUpwind1 = 1, kEno2 = 2, kWeno5 = 5 };
-enum Dyn { kTranslation = 0, kBall = 1, kDoubleIntegrator = 2, kRelDubins = 3, kDubins4D = 4 };
+enum Dyn {
+    kTranslation = 0,
+    kBall = 1,
+    kDoubleIntegrator = 2,
+    kRelDubins = 3,
+    kDubins4D = 4,
+    kRockets = 5
+};
 
 // How a stage kernel combines the right-hand side L(Vs) with its inputs:
 //   kRhs      out = L(Vs)
@@ -38,7 +45,8 @@ struct StageArgs {
     T prm[8];
     T dt, wb, w2, den;
     int combine;
-    int tube;
+    int tube;         // out = min(out, v0[node])
+    int vi;           // restricted update: L = min(L, 0) (variational-inequality tube)
 };
 
 struct AlphaArgs {

@@ -57,6 +57,9 @@ hipError_t launch_stage_t(int ndim, int space, int dyn, const StageArgs<T> &a, h
     case kDubins4D:
         if (ndim == 4) return launch_space<T, 4, kDubins4D, SPACES>(space, a, s);
         break;
+    case kRockets:
+        if (ndim == 3) return launch_space<T, 3, kRockets, SPACES>(space, a, s);
+        break;
     }
     return hipErrorInvalidValue;
 }

@@ -220,6 +220,17 @@ __device__ inline T hamiltonian(const StageArgs<T> &a, const int *ii, const T *p
         const T s = global_ptr(a.tab)[a.tab_off[2] + 2 * a.n[2] + ii[2]];
         return -p[0] * (-ve + vp * c) - p[1] * (vp * s) - we * fabs(p[0] * y - p[1] * x - p[2]) +
                wp * fabs(p[2]);
+    } else if constexpr (DYN == kRockets) {
+        // (x, z, th): p.f = p1 a cos th + p2 (a sin th + a - g) + ue (p1 x - p3)
+        // + up (p2 x + p3), evader ue maximising, pursuer up minimising
+        const T am = a.prm[0], grav = a.prm[1], um = a.prm[2];
+        const T x = global_ptr(a.tab)[a.tab_off[0] + ii[0]];
+        const T c = global_ptr(a.tab)[a.tab_off[2] + a.n[2] + ii[2]];
+        const T s = global_ptr(a.tab)[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+        const T drift1 = am * c;
+        const T drift2 = am * s + am - grav;
+        return -p[0] * drift1 - p[1] * drift2 - um * fabs(p[0] * x - p[2]) +
+               um * fabs(p[1] * x + p[2]);
     } else {
         const T wm = a.prm[0], am = a.prm[1];
         const T c = global_ptr(a.tab)[a.tab_off[2] + a.n[2] + ii[2]];
@@ -256,7 +267,8 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
         pbar[d] = (pp[d] + pm[d]) * T(0.5);
         diss += a.alpha[d] * ((pp[d] - pm[d]) * T(0.5));
     }
-    const T l = -(hamiltonian<T, D, DYN>(a, ii, pbar) - diss);
+    T l = -(hamiltonian<T, D, DYN>(a, ii, pbar) - diss);
+    if (a.vi && l > T(0)) l = T(0);
 
     T val;
     if (a.combine == kRhs) {

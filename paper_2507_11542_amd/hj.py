@@ -19,17 +19,17 @@ LIB_PATH = os.path.join(_HERE, "libhj.so")
 HJ_OK, HJ_E_ARG, HJ_E_OOM, HJ_E_DEVICE, HJ_E_STATE, HJ_E_NUMERIC, HJ_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 HJ_FP64, HJ_FP32 = 0, 1
-HJ_SET, HJ_TUBE = 0, 1
+HJ_SET, HJ_TUBE, HJ_TUBE_VI, HJ_TUBE_OUTPUTS = 0, 1, 2, 3
 HJ_UPWIND1, HJ_ENO2, HJ_WENO5 = 1, 2, 5
 HJ_RK1, HJ_RK2, HJ_RK3 = 1, 2, 3
 HJ_DYN_TRANSLATION, HJ_DYN_BALL, HJ_DYN_DOUBLE_INTEGRATOR, HJ_DYN_REL_DUBINS, \
-    HJ_DYN_DUBINS4D = 0, 1, 2, 3, 4
+    HJ_DYN_DUBINS4D, HJ_DYN_ROCKETS = 0, 1, 2, 3, 4, 5
 
 SPACE = {"upwind1": HJ_UPWIND1, "eno2": HJ_ENO2, "weno5": HJ_WENO5}
 DYN = {"translation": HJ_DYN_TRANSLATION, "ball": HJ_DYN_BALL,
        "double_integrator": HJ_DYN_DOUBLE_INTEGRATOR, "rel_dubins": HJ_DYN_REL_DUBINS,
-       "dubins4d": HJ_DYN_DUBINS4D}
-MODE = {"set": HJ_SET, "tube": HJ_TUBE}
+       "dubins4d": HJ_DYN_DUBINS4D, "rockets": HJ_DYN_ROCKETS}
+MODE = {"set": HJ_SET, "tube": HJ_TUBE, "tube_vi": HJ_TUBE_VI, "tube_out": HJ_TUBE_OUTPUTS}
 PREC = {"fp64": HJ_FP64, "fp32": HJ_FP32}
 
 STATUS_NAMES = {HJ_OK: "HJ_OK", HJ_E_ARG: "HJ_E_ARG", HJ_E_OOM: "HJ_E_OOM",
@@ -58,6 +58,7 @@ def _load():
     lib.hj_solve.argtypes = [P, P, P, D, D, I, P]
     lib.hj_step.argtypes = [P, P, P, PD, D, I, PD, P]
     lib.hj_solve_mixed.argtypes = [P, P, P, D, D, I, D, P]
+    lib.hj_solve_outputs.argtypes = [P, P, P, D, PD, I, I, P]
     lib.hj_rhs.argtypes = [P, P, P, P]
     lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
     lib.hj_grid_destroy.argtypes = [P]
@@ -72,7 +73,7 @@ def _load():
     lib.hj_batch_wait.argtypes = [P, P, PD, PI64]
     lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
-                 "hj_solve_mixed",
+                 "hj_solve_mixed", "hj_solve_outputs",
                  "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_grid_set_workspace",
                  "hj_batch_create",
                  "hj_batch_config", "hj_solve_batch", "hj_step_batch", "hj_batch_wait",
@@ -146,6 +147,13 @@ def hj_set_scheme(g, space: int = HJ_WENO5, time: int = HJ_RK3, cfl: float = 0.8
 def hj_solve(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, stream=None):
     _check(_lib.hj_solve(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
                          _stream(stream)))
+
+
+def hj_solve_outputs(g, V0, V_outs, t0: float, times: Sequence[float], mode: int = HJ_SET,
+                     stream=None):
+    ts = (ctypes.c_double * len(times))(*[float(t) for t in times])
+    _check(_lib.hj_solve_outputs(g, _ptr(V0), _ptr(V_outs), float(t0), ts, len(times),
+                                 int(mode), _stream(stream)))
 
 
 def hj_solve_mixed(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, band: float = -1.0,
@@ -298,6 +306,11 @@ class Grid:
 
     def solve(self, V0, V_out, t0, tf, mode="set", stream=None):
         hj_solve(self.handle, V0, V_out, t0, tf, MODE[mode], stream)
+
+    def solve_outputs(self, V0, V_outs, t0, times, mode="set", stream=None):
+        """V_outs: device array of len(times) * prod(n) elements (for example a
+        tensor of shape (len(times),) + n)."""
+        hj_solve_outputs(self.handle, V0, V_outs, t0, times, MODE[mode], stream)
 
     def step(self, V, V0, t, tf, mode="set", stream=None):
         return hj_step(self.handle, V, V0, t, tf, MODE[mode], stream)
