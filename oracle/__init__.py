@@ -15,6 +15,8 @@ Functions and the paper passages they follow:
 - ``solve``     full CFL-constrained solve over tspan (Sec. 5, Sec. 6.1 tube)
 - ``solve_outputs`` the same through a list of output times (Sec. 6.1, the
                 global steps of the rockets game)
+- ``shapes``    implicit-surface initial values and their Boolean
+                combinations (Sec. 2.2, Fig. 4)
 
 Every function is pinned by a ``-m "not gpu"`` test against closed forms,
 invariants, polynomial reproduction, convergence order or brute force; the
@@ -40,6 +42,8 @@ SCHEMES = {"upwind1": 1, "eno2": 2, "weno5": 5}
 DYNAMICS = {"translation": 0, "ball": 1, "double_integrator": 2,
             "rel_dubins": 3, "dubins4d": 4, "rockets": 5}
 MODES = {"set": 0, "tube": 1, "tube_vi": 2, "tube_out": 3}
+SHAPES = {"sphere": 0, "cylinder": 1, "box": 2, "ellipsoid": 3}
+OPS = {"union": 0, "intersect": 1, "subtract": 2}
 
 _lib = None
 
@@ -78,6 +82,8 @@ def _load():
     lib.orc_solve.restype = L
     lib.orc_solve_outputs.argtypes = [I, P, P, P, U, I, P, I, I, I, D, P, D, P, L, I, P]
     lib.orc_solve_outputs.restype = L
+    lib.orc_shapes.argtypes = [I, P, P, P, U, I, P, P, P, P, P, P, P]
+    lib.orc_shapes.restype = I
     lib.orc_set_threads.argtypes = [I]
     lib.orc_set_threads.restype = I
     _lib = lib
@@ -218,3 +224,32 @@ def solve_outputs(v0, n, lo, hi, periodic, dynamics, params, times, scheme="weno
     if k < 0:
         raise RuntimeError("oracle solve failed (%d)" % k)
     return outs, int(k)
+
+
+def shapes(n, lo, hi, periodic, shape_list):
+    """V0 from implicit surfaces (Sec. 2.2).  shape_list: dicts with keys
+    kind ("sphere", "cylinder", "box", "ellipsoid"), op ("union",
+    "intersect", "subtract"; ignored for the first), axes (axis indices,
+    empty = all), center, size (box half-widths / ellipsoid weights) and
+    radius."""
+    lib = _load()
+    n, lo, hi, mask = _grid_args(n, lo, hi, periodic)
+    k = len(shape_list)
+    kinds = np.array([SHAPES[s["kind"]] for s in shape_list], dtype=np.int32)
+    ops = np.array([OPS[s.get("op", "union")] for s in shape_list], dtype=np.int32)
+    masks = np.array([sum(1 << a for a in s.get("axes", ())) for s in shape_list],
+                     dtype=np.uint32)
+    centers = np.zeros((k, 4))
+    sizes = np.zeros((k, 4))
+    for i, s in enumerate(shape_list):
+        c = list(s.get("center", ()))
+        z = list(s.get("size", ()))
+        centers[i, : len(c)] = c
+        sizes[i, : len(z)] = z
+    radii = np.array([float(s.get("radius", 0.0)) for s in shape_list])
+    out = np.empty(tuple(int(v) for v in n), dtype=np.float64)
+    rc = lib.orc_shapes(len(n), _ptr(n), _ptr(lo), _ptr(hi), mask, k, _ptr(kinds), _ptr(ops),
+                        _ptr(masks), _ptr(centers), _ptr(sizes), _ptr(radii), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle shapes: bad grid or no shapes")
+    return out

@@ -22,6 +22,8 @@
  *     restricted to non-increasing values                [Sec. 6.1, the min[0,H] form]
  *   - tube update at output times only, output times    [Sec. 6.1, the global steps]
  *   - the rockets launch game (x, z, theta)              [Sec. 6.1, eq. ham_def]
+ *   - implicit-surface initial value functions: sphere, cylinder, box,
+ *     ellipsoid, combined by union / intersection / difference  [Sec. 2.2, Fig. 4]
  *
  * Readings where the paper is silent or garbled (all are also listed in the
  * design notes):
@@ -727,6 +729,84 @@ long orc_solve_outputs(int nd, const long *n, const double *lo, const double *hi
     free(l);
     grid_free(&g);
     return steps;
+}
+
+/* ------------------------------------------------- implicit surfaces */
+
+/* Sec. 2.2: V0 as a function of the node coordinates, negative inside the
+ * shape.  A shape takes part along the axes of its mask (all axes for a
+ * sphere or a zero mask); coordinate differences are plain (no wrap on a
+ * periodic axis).
+ *   SPHERE, CYLINDER  sqrt(sum (x_d - c_d)^2) - r           (signed distance)
+ *   BOX               |max(q, 0)|_2 + min(max_d q_d, 0),
+ *                     q_d = |x_d - c_d| - h_d                (signed distance)
+ *   ELLIPSOID         sum w_d (x_d - c_d)^2 - r              (the quadratic
+ *                     form of the ellipsoid listing, weights w = (1, 4, 9))
+ * Shapes combine left to right (Fig. 4): union min(v, s), intersection
+ * max(v, s), difference max(v, -s). */
+enum { ORC_SPHERE = 0, ORC_CYLINDER = 1, ORC_BOX = 2, ORC_ELLIPSOID = 3 };
+enum { ORC_UNION = 0, ORC_INTERSECT = 1, ORC_SUBTRACT = 2 };
+
+static double shape_value(int nd, int kind, unsigned mask, const double *c,
+                          const double *size, double r, const double *x)
+{
+    if (kind == ORC_SPHERE || mask == 0) mask = (1u << nd) - 1u;
+    if (kind == ORC_BOX) {
+        double outside = 0.0, inside = -INFINITY;
+        for (int d = 0; d < nd; ++d) {
+            if (!((mask >> d) & 1u)) continue;
+            double q = fabs(x[d] - c[d]) - size[d];
+            if (q > 0.0) outside = outside + q * q;
+            if (q > inside) inside = q;
+        }
+        return sqrt(outside) + (inside < 0.0 ? inside : 0.0);
+    }
+    double acc = 0.0;
+    for (int d = 0; d < nd; ++d) {
+        if (!((mask >> d) & 1u)) continue;
+        double t = x[d] - c[d];
+        if (kind == ORC_ELLIPSOID)
+            acc = acc + size[d] * (t * t);
+        else
+            acc = acc + t * t;
+    }
+    if (kind == ORC_ELLIPSOID) return acc - r;
+    return sqrt(acc) - r;
+}
+
+/* V at every node from nshapes shapes (kinds, ops, masks, centers and sizes
+ * as nshapes x 4 arrays, radii). */
+int orc_shapes(int nd, const long *n, const double *lo, const double *hi,
+               unsigned pmask, int nshapes, const int *kinds, const int *ops,
+               const unsigned *masks, const double *centers, const double *sizes,
+               const double *radii, double *out)
+{
+    ogrid g;
+    memset(&g, 0, sizeof(g));
+    if (nshapes < 1 || grid_init(&g, nd, n, lo, hi, pmask) != 0) {
+        grid_free(&g);
+        return -1;
+    }
+    for (long node = 0; node < g.total; ++node) {
+        double x[ORC_MAXD] = {0, 0, 0, 0};
+        for (int d = 0; d < nd; ++d) x[d] = g.x[d][axis_index(&g, node, d)];
+        double v = 0.0;
+        for (int k = 0; k < nshapes; ++k) {
+            double sv = shape_value(nd, kinds[k], masks[k], &centers[4 * k], &sizes[4 * k],
+                                    radii[k], x);
+            if (k == 0)
+                v = sv;
+            else if (ops[k] == ORC_UNION)
+                v = sv < v ? sv : v;
+            else if (ops[k] == ORC_INTERSECT)
+                v = sv > v ? sv : v;
+            else
+                v = -sv > v ? -sv : v;
+        }
+        out[node] = v;
+    }
+    grid_free(&g);
+    return 0;
 }
 
 /* number of host threads used by the node loops (0 or less: all cores) */

@@ -57,9 +57,16 @@ MUTATIONS = {
     "vi_restricts_nothing": ("if (mode == ORC_TUBE_VI && l > 0.0) l = 0.0;", ""),
     "tube_out_every_step": ("const int step_mode = mode == ORC_TUBE_OUT ? ORC_SET : mode;",
                             "const int step_mode = mode == ORC_TUBE_OUT ? ORC_TUBE : mode;"),
+    "box_inside_term_dropped": ("return sqrt(outside) + (inside < 0.0 ? inside : 0.0);",
+                                "return sqrt(outside);"),
+    "ellipsoid_weight_outside_square": ("acc = acc + size[d] * (t * t);",
+                                        "acc = acc + (size[d] * t) * (size[d] * t);"),
+    "sphere_ignores_center": ("        double t = x[d] - c[d];\n", "        double t = x[d];\n"),
+    "union_takes_max": ("v = sv < v ? sv : v;", "v = sv > v ? sv : v;"),
+    "subtract_sign": ("v = -sv > v ? -sv : v;", "v = sv > v ? sv : v;"),
 }
 
-PIN_FILES = ("test_oracle_pins.py", "test_oracle_rockets_tubes.py")
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_rockets_tubes.py", "test_oracle_shapes.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
