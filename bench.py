@@ -229,14 +229,15 @@ def bench_served(args):
 
     n = args.serve_requests
     base = inputs.serving_stream(count=n, rate=1.0, seed=0)
-    v0_cache = {k: r.problem.v0().astype(np.float32) for k, r in enumerate(base)}
+    v0_cache = ({} if args.device_v0 else
+                {k: r.problem.v0().astype(np.float32) for k, r in enumerate(base)})
 
     def at_rate(rate):
         return [inputs.Request(r.arrival / rate, r.problem) for r in base]
 
     def served(rate):
         print("[bench] served at %.3g req/s" % rate, file=sys.stderr, flush=True)
-        be = GpuBackend(prec="fp32", v0_cache=v0_cache)
+        be = GpuBackend(prec="fp32", v0_cache=v0_cache, device_v0=args.device_v0)
         try:
             rep, _ = Server(be, hbm_budget=int(args.serve_budget_gib * (1 << 30)),
                             macro_steps=args.macro_steps,
@@ -247,7 +248,8 @@ def bench_served(args):
 
     def plain(rate):
         print("[bench] plain at %.3g req/s" % rate, file=sys.stderr, flush=True)
-        rep, _ = run_plain(at_rate(rate), prec="fp32", v0_cache=v0_cache)
+        rep, _ = run_plain(at_rate(rate), prec="fp32", v0_cache=v0_cache,
+                           device_v0=args.device_v0)
         return rep.as_dict()
 
     sat = served(1e9)  # everything arrives at once: saturated throughput
@@ -260,6 +262,8 @@ def bench_served(args):
     return {"workload": "%d requests, thirds DI 101^2..401^2 / rel-Dubins 51^3..121^3 / "
                         "4-D Dubins 41^4..61^4, WENO5+LF+RK3, FP32, Poisson (seed 0)" % n,
             "macro_steps": args.macro_steps, "macro_updates": args.macro_updates,
+            "v0": ("built on the GPU from each request's shape recipe (hj_init_shapes)"
+                   if args.device_v0 else "uploaded from the host per request"),
             "saturated_rate_req_per_s": lam_sat, "served": runs, "plain": plains,
             "served_vs_plain_updates_per_s":
                 sat["updates_per_s"] / plains["saturated"]["updates_per_s"]}
@@ -282,6 +286,9 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=96)
     ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.5, 0.9])
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--host-v0", dest="device_v0", action="store_false",
+                    help="serving legs upload V0 from the host instead of building it on "
+                         "the GPU from the request's shape recipe")
     ap.add_argument("--macro-steps", type=int, default=64,
                     help="most RK steps per instance in one serving macro-iteration")
     ap.add_argument("--macro-updates", type=float, default=1.5e8,

@@ -93,6 +93,36 @@ typedef enum {
     HJ_DYN_ROCKETS = 5
 } hj_dyn;
 
+/* Implicit surfaces (Sec. 2.2, Fig. 4): a shape is negative inside.  It takes
+ * part along the axes of `axes` (bit d: axis d; 0 = all axes; a sphere always
+ * uses all axes), with plain coordinate differences (no wrap on a periodic
+ * axis).
+ *   HJ_SHAPE_SPHERE, HJ_SHAPE_CYLINDER  sqrt(sum (x_d - center_d)^2) - radius
+ *                                       (signed distance; a cylinder is
+ *                                       infinite along the axes it leaves out)
+ *   HJ_SHAPE_BOX        signed distance to the box |x_d - center_d| <= size_d
+ *   HJ_SHAPE_ELLIPSOID  sum size_d (x_d - center_d)^2 - radius (the quadratic
+ *                       form of the ellipsoid listing, weights e.g. 1, 4, 9)
+ * Shapes combine left to right with their op (the first one's is ignored):
+ * HJ_OP_UNION min(v, s), HJ_OP_INTERSECT max(v, s), HJ_OP_SUBTRACT
+ * max(v, -s). */
+typedef enum {
+    HJ_SHAPE_SPHERE = 0,
+    HJ_SHAPE_CYLINDER = 1,
+    HJ_SHAPE_BOX = 2,
+    HJ_SHAPE_ELLIPSOID = 3
+} hj_shape_kind;
+typedef enum { HJ_OP_UNION = 0, HJ_OP_INTERSECT = 1, HJ_OP_SUBTRACT = 2 } hj_shape_op;
+typedef struct {
+    int32_t kind;      /* hj_shape_kind */
+    int32_t op;        /* hj_shape_op */
+    uint32_t axes;     /* axis mask, 0 = all */
+    uint32_t reserved; /* 0 */
+    double center[4];
+    double size[4];    /* box half-widths, ellipsoid weights */
+    double radius;     /* sphere/cylinder radius, ellipsoid level */
+} hj_shape;
+
 /* Sec. 2.1 (createGrid(min, max, N, pdim)).  ndim in [1, 4]; N[i] nodes on
  * axis i in [lo[i], hi[i]]; bit i of periodic_mask makes axis i periodic.  A
  * bounded axis has both ends as nodes, dx = (hi-lo)/(N-1); a periodic axis
@@ -119,6 +149,15 @@ hj_status hj_set_scheme(hj_grid_t g, hj_space space, hj_time time, double cfl);
  * V0.  HJ_E_ARG on NULL pointers, overlap, tf < t0 or non-finite times. */
 hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double tf,
                    hj_mode mode, void *hip_stream);
+
+/* Sec. 2.2: V_out (device, prod(N) elements of the grid's precision) at every
+ * node from the nshapes shapes (host array, 1..16 of them), evaluated in FP64
+ * on the device (FP32 grids store the rounded value), so a solve's initial
+ * values need no host-to-device copy.  Enqueued on hip_stream.  HJ_E_ARG on
+ * NULL pointers, nshapes out of range, unknown kinds or ops, or masks naming
+ * axes >= ndim. */
+hj_status hj_init_shapes(hj_grid_t g, void *V_out, const hj_shape *shapes, int nshapes,
+                         void *hip_stream);
 
 /* Sec. 6.1 (the global time steps of the rockets game) with the Sec. 5 loop:
  * a solve from V0 at t0 through the output times times[0..ntimes) (host

@@ -21,6 +21,8 @@
 
 using namespace hj;
 
+static_assert(sizeof(hj_shape) == 88, "hj_shape layout of include/hj.h");
+
 namespace {
 
 thread_local std::string g_err;
@@ -441,6 +443,50 @@ hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double t
     HJ_HIP(hipMemcpyAsync(V_out, V0, g->bytes(), hipMemcpyDeviceToDevice, st), "copy V0");
     if (g->prec == HJ_FP64) return run_steps<double>(g, V_out, V0, mode, hs, st);
     return run_steps<float>(g, V_out, V0, mode, hs, st);
+}
+
+hj_status hj_init_shapes(hj_grid_t g, void *V_out, const hj_shape *shapes, int nshapes,
+                         void *hip_stream)
+{
+    if (!g) return fail(HJ_E_ARG, "null grid handle");
+    if (!V_out || !shapes) return fail(HJ_E_ARG, "V_out and shapes must be non-NULL");
+    if (nshapes < 1 || nshapes > kMaxShapes)
+        return fail(HJ_E_ARG, "nshapes must be in [1, " + std::to_string(kMaxShapes) + "]");
+    ShapeArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const uint32_t all = (1u << g->nd) - 1u;
+    for (int k = 0; k < nshapes; ++k) {
+        const hj_shape &s = shapes[k];
+        if (s.kind < HJ_SHAPE_SPHERE || s.kind > HJ_SHAPE_ELLIPSOID)
+            return fail(HJ_E_ARG, "unknown shape kind in shape " + std::to_string(k));
+        if (k > 0 && (s.op < HJ_OP_UNION || s.op > HJ_OP_SUBTRACT))
+            return fail(HJ_E_ARG, "unknown shape op in shape " + std::to_string(k));
+        if (s.axes & ~all) return fail(HJ_E_ARG, "shape axes name an axis >= ndim");
+        ShapeDesc &d = a.s[k];
+        d.kind = s.kind;
+        d.op = s.op;
+        d.mask = (s.kind == HJ_SHAPE_SPHERE || s.axes == 0) ? all : s.axes;
+        for (int i = 0; i < kMaxDim; ++i) {
+            d.center[i] = s.center[i];
+            d.size[i] = s.size[i];
+        }
+        d.radius = s.radius;
+    }
+    a.tab = g->tab64;
+    a.out = V_out;
+    for (int d = 0; d < kMaxDim; ++d) {
+        a.n[d] = uint32_t(g->n[d]);
+        a.tab_off[d] = g->tab_off[d];
+    }
+    a.total = uint32_t(g->total);
+    a.nd = g->nd;
+    a.nshapes = nshapes;
+    a.fp32 = g->prec == HJ_FP32 ? 1 : 0;
+    hj_status s = use_device(g);
+    if (s != HJ_OK) return s;
+    hipError_t e = launch_shapes(a, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "shapes launch");
+    return HJ_OK;
 }
 
 hj_status hj_solve_outputs(hj_grid_t g, const void *V0, void *V_outs, double t0,

@@ -69,6 +69,34 @@ hipError_t launch_alpha(int ndim, int dyn, const AlphaArgs &a, double *partial, 
                         hipStream_t s);
 
 hipError_t launch_round_to_f32(const double *src, float *dst, uint32_t n, hipStream_t s);
+
+// Implicit-surface initial values (the shapes of include/hj.h, evaluated in
+// FP64 and stored as double or float).
+constexpr int kMaxShapes = 16;
+
+struct ShapeDesc {
+    int kind;
+    int op;
+    uint32_t mask;  // axes taking part (already resolved: never 0)
+    uint32_t pad;
+    double center[kMaxDim];
+    double size[kMaxDim];
+    double radius;
+};
+
+struct ShapeArgs {
+    const double *tab;  // per-axis [x | cos x | sin x] blocks
+    void *out;
+    uint32_t n[kMaxDim];
+    uint32_t tab_off[kMaxDim];
+    uint32_t total;
+    int nd;
+    int nshapes;
+    int fp32;  // store as float
+    ShapeDesc s[kMaxShapes];
+};
+
+hipError_t launch_shapes(const ShapeArgs &a, hipStream_t s);
 hipError_t launch_finalize_f64(const float *v32, const double *v0, double *out, uint32_t n,
                                double band, int tube, hipStream_t s);
 

@@ -32,6 +32,33 @@ DYN = {"translation": HJ_DYN_TRANSLATION, "ball": HJ_DYN_BALL,
 MODE = {"set": HJ_SET, "tube": HJ_TUBE, "tube_vi": HJ_TUBE_VI, "tube_out": HJ_TUBE_OUTPUTS}
 PREC = {"fp64": HJ_FP64, "fp32": HJ_FP32}
 
+SHAPE = {"sphere": 0, "cylinder": 1, "box": 2, "ellipsoid": 3}
+OP = {"union": 0, "intersect": 1, "subtract": 2}
+
+
+class HjShape(ctypes.Structure):
+    """struct hj_shape of include/hj.h"""
+    _fields_ = [("kind", ctypes.c_int32), ("op", ctypes.c_int32), ("axes", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("center", ctypes.c_double * 4),
+                ("size", ctypes.c_double * 4), ("radius", ctypes.c_double)]
+
+
+def make_shapes(shape_list) -> "ctypes.Array":
+    """hj_shape array from dicts with keys kind, op, axes (axis indices; empty
+    = all), center, size, radius (the names of include/hj.h)."""
+    arr = (HjShape * len(shape_list))()
+    for s, d in zip(arr, shape_list):
+        s.kind = SHAPE[d["kind"]]
+        s.op = OP[d.get("op", "union")]
+        s.axes = sum(1 << a for a in d.get("axes", ()))
+        for i, c in enumerate(d.get("center", ())):
+            s.center[i] = float(c)
+        for i, c in enumerate(d.get("size", ())):
+            s.size[i] = float(c)
+        s.radius = float(d.get("radius", 0.0))
+    return arr
+
+
 STATUS_NAMES = {HJ_OK: "HJ_OK", HJ_E_ARG: "HJ_E_ARG", HJ_E_OOM: "HJ_E_OOM",
                 HJ_E_DEVICE: "HJ_E_DEVICE", HJ_E_STATE: "HJ_E_STATE",
                 HJ_E_NUMERIC: "HJ_E_NUMERIC", HJ_E_UNSUPPORTED: "HJ_E_UNSUPPORTED"}
@@ -59,6 +86,7 @@ def _load():
     lib.hj_step.argtypes = [P, P, P, PD, D, I, PD, P]
     lib.hj_solve_mixed.argtypes = [P, P, P, D, D, I, D, P]
     lib.hj_solve_outputs.argtypes = [P, P, P, D, PD, I, I, P]
+    lib.hj_init_shapes.argtypes = [P, P, P, I, P]
     lib.hj_rhs.argtypes = [P, P, P, P]
     lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
     lib.hj_grid_destroy.argtypes = [P]
@@ -73,7 +101,7 @@ def _load():
     lib.hj_batch_wait.argtypes = [P, P, PD, PI64]
     lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
-                 "hj_solve_mixed", "hj_solve_outputs",
+                 "hj_solve_mixed", "hj_solve_outputs", "hj_init_shapes",
                  "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_grid_set_workspace",
                  "hj_batch_create",
                  "hj_batch_config", "hj_solve_batch", "hj_step_batch", "hj_batch_wait",
@@ -147,6 +175,12 @@ def hj_set_scheme(g, space: int = HJ_WENO5, time: int = HJ_RK3, cfl: float = 0.8
 def hj_solve(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, stream=None):
     _check(_lib.hj_solve(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
                          _stream(stream)))
+
+
+def hj_init_shapes(g, V_out, shape_list, stream=None):
+    arr = make_shapes(shape_list)
+    _check(_lib.hj_init_shapes(g, _ptr(V_out), ctypes.cast(arr, ctypes.c_void_p), len(arr),
+                               _stream(stream)))
 
 
 def hj_solve_outputs(g, V0, V_outs, t0: float, times: Sequence[float], mode: int = HJ_SET,
@@ -306,6 +340,10 @@ class Grid:
 
     def solve(self, V0, V_out, t0, tf, mode="set", stream=None):
         hj_solve(self.handle, V0, V_out, t0, tf, MODE[mode], stream)
+
+    def init_shapes(self, V_out, shape_list, stream=None):
+        """V_out <- the implicit surface of shape_list (dicts as in make_shapes)."""
+        hj_init_shapes(self.handle, V_out, shape_list, stream)
 
     def solve_outputs(self, V0, V_outs, t0, times, mode="set", stream=None):
         """V_outs: device array of len(times) * prod(n) elements (for example a

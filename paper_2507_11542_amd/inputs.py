@@ -70,6 +70,12 @@ class Problem:
         return sdf_cylinder(self.n, self.lo, self.hi, self.periodic, self.radius,
                             self.v0_axes)
 
+    def shapes(self) -> List[dict]:
+        """The same V0 as an implicit-surface recipe (a cylinder over the
+        v0 axes), for building it on the device."""
+        return [dict(kind="cylinder", axes=tuple(a for a in self.v0_axes if a < self.ndim),
+                     radius=self.radius)]
+
     def with_(self, **kw) -> "Problem":
         return dataclasses.replace(self, **kw)
 

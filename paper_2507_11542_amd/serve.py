@@ -218,7 +218,8 @@ class GpuBackend:
     requests that joined it (stream-ordered events, no host wait)."""
 
     def __init__(self, prec: str = "fp32", tile_nodes: int = 256, workgroups: int = 0,
-                 use_graph: bool = True, v0_cache: Optional[Dict[int, np.ndarray]] = None):
+                 use_graph: bool = True, v0_cache: Optional[Dict[int, np.ndarray]] = None,
+                 device_v0: bool = False):
         import torch
 
         from . import hj
@@ -230,6 +231,7 @@ class GpuBackend:
         self.elem = 4 if prec == "fp32" else 8
         self.cfg = (tile_nodes, workgroups, use_graph)
         self.v0_cache = v0_cache if v0_cache is not None else {}
+        self.device_v0 = device_v0  # build V0 from the problem's shape recipe on the GPU
         self.engines: Dict[Tuple, object] = {}
         self.streams: Dict[Tuple, object] = {}
         self.events: Dict[Tuple, object] = {}
@@ -250,21 +252,26 @@ class GpuBackend:
     def admit(self, j: Job):
         torch = self.torch
         p = j.problem
-        v0h = self.v0_cache.get(j.rid)
-        if v0h is None:
-            v0h = p.v0()
+        g = self.hj.Grid.from_problem(p, self.prec)
         try:
             with torch.cuda.stream(self.upload):
-                v0 = torch.from_numpy(np.ascontiguousarray(v0h)).to(self.device, self.dtype,
-                                                                     non_blocking=False)
+                if self.device_v0:
+                    v0 = torch.empty(tuple(p.n), dtype=self.dtype, device=self.device)
+                    g.init_shapes(v0, p.shapes(), self.upload)
+                else:
+                    v0h = self.v0_cache.get(j.rid)
+                    if v0h is None:
+                        v0h = p.v0()
+                    v0 = torch.from_numpy(np.ascontiguousarray(v0h)).to(
+                        self.device, self.dtype, non_blocking=False)
                 v = v0.clone()
                 a = torch.empty_like(v0)
                 b = torch.empty_like(v0)
                 ready = torch.cuda.Event()
                 ready.record(self.upload)
         except RuntimeError as e:  # torch reports device OOM as RuntimeError
+            g.close()
             raise MemoryError(str(e))
-        g = self.hj.Grid.from_problem(p, self.prec)
         g.set_workspace(a, b)
         j.dev = {"grid": g, "v0": v0, "v": v, "a": a, "b": b, "ready": ready}
         j.t = p.t0
@@ -322,9 +329,12 @@ class GpuBackend:
 
 def run_plain(requests: Sequence[inputs.Request], prec: str = "fp32",
               v0_cache: Optional[Dict[int, np.ndarray]] = None, keep_results: bool = False,
-              clock=time.perf_counter, sleep=time.sleep) -> Tuple[ServeReport, List[Job]]:
+              device_v0: bool = False, clock=time.perf_counter, sleep=time.sleep
+              ) -> Tuple[ServeReport, List[Job]]:
     """The same requests one at a time through hj_solve (no batching, no
-    graph): each starts when it has arrived and the previous one finished."""
+    graph): each starts when it has arrived and the previous one finished.
+    device_v0 builds V0 on the GPU from the problem's shape recipe, as the
+    serving backend can."""
     import torch
 
     from . import hj
@@ -341,11 +351,15 @@ def run_plain(requests: Sequence[inputs.Request], prec: str = "fp32",
             sleep(min(wait, 0.05))
             wait = j.arrival - (clock() - start)
         p = j.problem
-        v0h = (v0_cache or {}).get(j.rid)
-        v0 = torch.from_numpy(np.ascontiguousarray(v0h if v0h is not None else p.v0())).to(
-            "cuda", dtype)
-        out = torch.empty_like(v0)
         g = hj.Grid.from_problem(p, prec)
+        if device_v0:
+            v0 = torch.empty(tuple(p.n), dtype=dtype, device="cuda")
+            g.init_shapes(v0, p.shapes(), stream)
+        else:
+            v0h = (v0_cache or {}).get(j.rid)
+            v0 = torch.from_numpy(np.ascontiguousarray(v0h if v0h is not None else p.v0())).to(
+                "cuda", dtype)
+        out = torch.empty_like(v0)
         _, _, steps = g.schedule(p.t0, p.tf, stream)
         g.solve(v0, out, p.t0, p.tf, p.mode, stream)
         stream.synchronize()

@@ -57,6 +57,9 @@ def test_argument_errors_without_device():
     assert lib.hj_solve(None, None, None, 0.0, 1.0, 0, None) == hj.HJ_E_ARG
     ts = (ctypes.c_double * 2)(0.5, 1.0)
     assert lib.hj_solve_outputs(None, None, None, 0.0, ts, 2, 0, None) == hj.HJ_E_ARG
+    shp = hj.make_shapes([dict(kind="sphere", radius=1.0)])
+    assert lib.hj_init_shapes(None, None, ctypes.cast(shp, ctypes.c_void_p), 1,
+                              None) == hj.HJ_E_ARG
     assert lib.hj_step(None, None, None, None, 1.0, 0, None, None) == hj.HJ_E_ARG
     assert lib.hj_rhs(None, None, None, None) == hj.HJ_E_ARG
     assert lib.hj_batch_config(None, 4096, 1024, 1) == hj.HJ_E_ARG

@@ -144,3 +144,62 @@ def test_rockets_full_size_golden(orc):
         rows = data[data[:, 0] == o]
         vals = got[o].ravel()[rows[:, 1].astype(np.int64)]
         assert np.abs(vals - rows[:, 2]).max() <= TOL64, o
+
+
+# ------------------------------------------------ implicit-surface V0 on the GPU
+SHAPE_CASES = [
+    ("cylinder", [dict(kind="cylinder", axes=(0, 1), radius=1.3)]),
+    ("sphere_union_box", [dict(kind="sphere", center=(-0.5, 0.2, 0.0), radius=0.9),
+                          dict(kind="box", center=(0.8, -0.3, 0.4), size=(0.6, 0.4, 0.9),
+                               op="union")]),
+    ("ellipsoid_minus_sphere", [dict(kind="ellipsoid", size=(1.0, 4.0, 9.0), radius=2.0),
+                                dict(kind="sphere", center=(0.3, 0.0, 0.0), radius=0.4,
+                                     op="subtract")]),
+    ("box_intersect_cylinder", [dict(kind="box", axes=(0, 2), size=(1.2, 0.0, 0.8)),
+                                dict(kind="cylinder", axes=(1, 2), radius=1.0,
+                                     op="intersect")]),
+]
+
+
+@pytest.mark.parametrize("name,shapes", SHAPE_CASES, ids=[c[0] for c in SHAPE_CASES])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_init_shapes_match_oracle(orc, name, shapes, prec):
+    """hj_init_shapes equals the oracle's FP64 shapes (FP32: the same values
+    rounded once) on a ragged 3-D grid with a periodic axis."""
+    import torch
+
+    from gpu_util import torch_dtype
+    from paper_2507_11542_amd import hj
+
+    n, lo, hi, per = (45, 38, 29), (-2.0, -2.0, -3.1), (2.0, 2.0, 3.1), (False, False, True)
+    ref = orc.shapes(n, lo, hi, per, shapes)
+    g = hj.Grid(n, lo, hi, per, prec)
+    out = torch.empty(n, dtype=torch_dtype(prec), device="cuda")
+    try:
+        g.init_shapes(out, shapes, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+    finally:
+        g.close()
+    got = out.cpu().numpy()
+    if prec == "fp64":
+        assert np.abs(got - ref).max() <= 1e-15 * max(1.0, np.abs(ref).max())
+    else:
+        assert np.array_equal(got, ref.astype(np.float32))
+
+
+def test_served_with_device_v0_equals_alone():
+    """Serving with V0 built on the GPU gives the results of the same requests
+    solved alone from host-built V0, bit for bit."""
+    from gpu_util import gpu_solve
+    from paper_2507_11542_amd.serve import GpuBackend, Server
+
+    reqs = inputs.serving_stream(count=8, rate=300.0, seed=21, di_sizes=(41, 61),
+                                 rd_sizes=(21, 29), d4_sizes=(11, 15), horizon=(0.1, 0.3))
+    be = GpuBackend(prec="fp32", device_v0=True)
+    try:
+        rep, jobs = Server(be, hbm_budget=1 << 30, macro_steps=6).run(reqs, keep_results=True)
+    finally:
+        be.close()
+    assert rep.completed == len(reqs)
+    for j in jobs:
+        assert np.array_equal(j.result, gpu_solve(j.problem, "fp32"))
