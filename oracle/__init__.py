@@ -38,7 +38,7 @@ _LIB = os.path.join(_HERE, "libhj_oracle.so")
 # a test may point the shim at a deliberately mutated build of the oracle
 _LIB = os.environ.get("HJ_ORACLE_LIB", _LIB)
 
-SCHEMES = {"upwind1": 1, "eno2": 2, "weno5": 5}
+SCHEMES = {"upwind1": 1, "eno2": 2, "eno3": 3, "weno5": 5}
 DYNAMICS = {"translation": 0, "ball": 1, "double_integrator": 2,
             "rel_dubins": 3, "dubins4d": 4, "rockets": 5}
 MODES = {"set": 0, "tube": 1, "tube_vi": 2, "tube_out": 3}

@@ -13,6 +13,7 @@
  *   - one-sided derivatives p-/p+ per axis:
  *       first order upwind                               [Sec. 3, eq. (fwd_bck_differencing), Sec. 3.1]
  *       ENO2 from the divided-difference table           [Sec. 3.2]
+ *       ENO3 (third divided differences, the c* choice)  [Sec. 3.2, ENO3 paragraph]
  *       WENO5 (Jiang-Peng weights)                       [Sec. 3.3]
  *   - Lax-Friedrichs numerical Hamiltonian               [Sec. 4, LF equation]
  *   - dissipation alpha_i = max over nodes of |dH/dp_i| bound, CFL dt [Sec. 4]
@@ -35,6 +36,13 @@
  *       p- = D1_{i-1/2} + dx*m(D2_{i-1}, D2_i), p+ = D1_{i+1/2} - dx*m(D2_i, D2_{i+1}),
  *       m(a,b) = a if |a| <= |b| else b (the <= tie rule printed for ENO3).
  *   R3  WENO5: Jiang-Peng with eps = 1e-6*max(v_k^2) + 1e-99.
+ *   R24 ENO3 (Osher-Fedkiw's HJ ENO3, which the paper follows):
+ *       D3_{j+1/2} = (D2_{j+1} - D2_j)/(3dx) (with the reciprocal 1/(3dx));
+ *       k = i-1 for p-, k = i for p+; Q1' = D1_{k+1/2};
+ *       c = D2_k, k* = k-1 if |D2_k| <= |D2_{k+1}|, else c = D2_{k+1}, k* = k;
+ *       Q2' = c (2(i-k)-1) dx;
+ *       c* = D3_{k*+1/2} if |D3_{k*+1/2}| <= |D3_{k*+3/2}| else D3_{k*+3/2};
+ *       Q3' = c* (3(i-k*)^2 - 6(i-k*) + 2) dx^2; p = (Q1' + Q2') + Q3'.
  *   R4  alpha_i = max over grid nodes of max over controls |f_i(x,u,d)|;
  *       computed once per solve (it does not depend on V).
  *   R5  dt = cfl / sum_i alpha_i/dx_i, fixed for all stages of a step.
@@ -74,7 +82,7 @@
 
 /* scheme, integrator and dynamics codes of this file (the Python shim maps
  * names to them; nothing outside this file shares them) */
-enum { ORC_UPWIND1 = 1, ORC_ENO2 = 2, ORC_WENO5 = 5 };
+enum { ORC_UPWIND1 = 1, ORC_ENO2 = 2, ORC_ENO3 = 3, ORC_WENO5 = 5 };
 enum { ORC_TRANSLATION = 0, ORC_BALL = 1, ORC_DOUBLE_INTEGRATOR = 2,
        ORC_REL_DUBINS = 3, ORC_DUBINS4D = 4, ORC_ROCKETS = 5 };
 enum { ORC_SET = 0, ORC_TUBE = 1, ORC_TUBE_VI = 2, ORC_TUBE_OUT = 3 };
@@ -87,6 +95,7 @@ typedef struct {
     double lo[ORC_MAXD], hi[ORC_MAXD], dx[ORC_MAXD];
     double inv_dx[ORC_MAXD];  /* 1/dx */
     double inv_2dx[ORC_MAXD]; /* 1/(2 dx) */
+    double inv_3dx[ORC_MAXD]; /* 1/(3 dx) */
     int periodic[ORC_MAXD];
     double *x[ORC_MAXD]; /* node coordinates per axis */
     double *cs[ORC_MAXD]; /* cos of the node coordinates */
@@ -117,6 +126,7 @@ static int grid_init(ogrid *g, int nd, const long *n, const double *lo,
                                   : (hi[d] - lo[d]) / (double)(n[d] - 1);
         g->inv_dx[d] = 1.0 / g->dx[d];
         g->inv_2dx[d] = 1.0 / (2.0 * g->dx[d]);
+        g->inv_3dx[d] = 1.0 / (3.0 * g->dx[d]);
         g->total *= n[d];
     }
     /* C order: the last axis is the fastest */
@@ -289,6 +299,40 @@ static void derivs_at(const ogrid *g, const double *v, long node, int d,
         for (int k = 0; k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) * g->inv_2dx[d];
         *pm = d1[1] + dx * eno_pick(d2[0], d2[1]);
         *pp = d1[2] - dx * eno_pick(d2[1], d2[2]);
+        return;
+    }
+    if (scheme == ORC_ENO3) {
+        /* s[0..6] = v_{i-3} .. v_{i+3}; the table of reading R24:
+         * d1[j] = D1 at i-5/2+j, d2[j] = D2 at i-2+j, d3[j] = D3 at i-3/2+j */
+        double s[7], d1[6], d2[5], d3[4];
+        for (int k = 0; k < 7; ++k) s[k] = line_value(g, v, node, d, i - 3 + k);
+        for (int k = 0; k < 6; ++k) d1[k] = (s[k + 1] - s[k]) * inv_dx;
+        for (int k = 0; k < 5; ++k) d2[k] = (d1[k + 1] - d1[k]) * g->inv_2dx[d];
+        for (int k = 0; k < 4; ++k) d3[k] = (d2[k + 1] - d2[k]) * g->inv_3dx[d];
+        double dxx = dx * dx;
+        /* p-: k = i-1, so i-k = 1 and Q2' = c dx; k* = i-2 (factor 2) or i-1 (-1) */
+        double c, cs, f;
+        if (fabs(d2[1]) <= fabs(d2[2])) {
+            c = d2[1];
+            cs = eno_pick(d3[0], d3[1]);
+            f = 2.0;
+        } else {
+            c = d2[2];
+            cs = eno_pick(d3[1], d3[2]);
+            f = -1.0;
+        }
+        *pm = (d1[2] + c * dx) + cs * (f * dxx);
+        /* p+: k = i, so i-k = 0 and Q2' = -c dx; k* = i-1 (factor -1) or i (2) */
+        if (fabs(d2[2]) <= fabs(d2[3])) {
+            c = d2[2];
+            cs = eno_pick(d3[1], d3[2]);
+            f = -1.0;
+        } else {
+            c = d2[3];
+            cs = eno_pick(d3[2], d3[3]);
+            f = 2.0;
+        }
+        *pp = (d1[3] - c * dx) + cs * (f * dxx);
         return;
     }
     /* WENO5: s[0..6] = v_{i-3} .. v_{i+3}; D1 at half points i-5/2 .. i+5/2 */

@@ -57,6 +57,14 @@ MUTATIONS = {
     "vi_restricts_nothing": ("if (mode == ORC_TUBE_VI && l > 0.0) l = 0.0;", ""),
     "tube_out_every_step": ("const int step_mode = mode == ORC_TUBE_OUT ? ORC_SET : mode;",
                             "const int step_mode = mode == ORC_TUBE_OUT ? ORC_TUBE : mode;"),
+    "eno3_minus_factor_swapped": ("            cs = eno_pick(d3[0], d3[1]);\n            f = 2.0;",
+                                  "            cs = eno_pick(d3[0], d3[1]);\n            f = -1.0;"),
+    "eno3_picks_larger_third": ("            c = d2[3];\n            cs = eno_pick(d3[2], d3[3]);",
+                                "            c = d2[3];\n            cs = eno_pick(d3[3], d3[2]) == d3[3] ? d3[2] : d3[3];"),
+    "eno3_third_difference_scale": ("d3[k] = (d2[k + 1] - d2[k]) * g->inv_3dx[d];",
+                                    "d3[k] = (d2[k + 1] - d2[k]) * g->inv_2dx[d];"),
+    "eno3_right_first_difference": ("*pp = (d1[3] - c * dx) + cs * (f * dxx);",
+                                    "*pp = (d1[2] - c * dx) + cs * (f * dxx);"),
     "box_inside_term_dropped": ("return sqrt(outside) + (inside < 0.0 ? inside : 0.0);",
                                 "return sqrt(outside);"),
     "ellipsoid_weight_outside_square": ("acc = acc + size[d] * (t * t);",
