@@ -60,8 +60,9 @@ typedef enum { HJ_FP64 = 0, HJ_FP32 = 1 } hj_precision;
 typedef enum { HJ_SET = 0, HJ_TUBE = 1, HJ_TUBE_VI = 2, HJ_TUBE_OUTPUTS = 3 } hj_mode;
 
 /* One-sided derivative approximations (Sec. 3): first order (Sec. 3.1, halo
- * 1), ENO2 (Sec. 3.2, halo 2), WENO5 (Sec. 3.3, halo 3). */
-typedef enum { HJ_UPWIND1 = 1, HJ_ENO2 = 2, HJ_WENO5 = 5 } hj_space;
+ * 1), ENO2 (Sec. 3.2, halo 2), ENO3 (Sec. 3.2's third-order paragraph, halo
+ * 3), WENO5 (Sec. 3.3, halo 3). */
+typedef enum { HJ_UPWIND1 = 1, HJ_ENO2 = 2, HJ_ENO3 = 3, HJ_WENO5 = 5 } hj_space;
 
 /* TVD Runge-Kutta order (Sec. 5): forward Euler, Shu-Osher RK2, RK3. */
 typedef enum { HJ_RK1 = 1, HJ_RK2 = 2, HJ_RK3 = 3 } hj_time;
@@ -203,7 +204,7 @@ hj_status hj_get_schedule(hj_grid_t g, double t0, double tf, double *alpha, doub
 
 /* ------------------------------------------------------------------------
  * Batched solves.  n independent grids that share ndim, dynamics kind,
- * derivative scheme (ENO2 or WENO5), RK order (2 or 3), precision and device
+ * derivative scheme (ENO2, ENO3 or WENO5), RK order (2 or 3), precision and device
  * advance together: one fused launch per RK-stage round covers the tiles of
  * every instance still running, so instances of any size and step count run
  * side by side, and each keeps its own alpha, dt and FP64 time t on the device

@@ -27,7 +27,7 @@ namespace {
 
 thread_local std::string g_err;
 
-int halo_of(int space) { return space == HJ_UPWIND1 ? 1 : (space == HJ_ENO2 ? 2 : 3); }
+int halo_of(int space) { return space == HJ_UPWIND1 ? 1 : (space == HJ_ENO2 ? 2 : 3); }  // ENO3, WENO5: 3
 
 // Testing hook: HJ_FAULT_OOM=1 makes every device allocation of the library
 // report HJ_E_OOM without calling the allocator.
@@ -160,6 +160,7 @@ StageArgs<T> base_args(hj_grid_t g)
         a.dx[d] = T(g->dx[d]);
         a.inv_dx[d] = T(1.0 / g->dx[d]);
         a.inv_2dx[d] = T(1.0 / (2.0 * g->dx[d]));
+        a.inv_3dx[d] = T(1.0 / (3.0 * g->dx[d]));
         a.alpha[d] = T(g->alpha[d]);
     }
     a.total = uint32_t(g->total);
@@ -394,7 +395,7 @@ hj_status hj_set_dynamics(hj_grid_t g, hj_dyn kind, const double *params, int np
 hj_status hj_set_scheme(hj_grid_t g, hj_space space, hj_time time, double cfl)
 {
     if (!g) return fail(HJ_E_ARG, "null grid handle");
-    if (space != HJ_UPWIND1 && space != HJ_ENO2 && space != HJ_WENO5)
+    if (space != HJ_UPWIND1 && space != HJ_ENO2 && space != HJ_ENO3 && space != HJ_WENO5)
         return fail(HJ_E_ARG, "unknown spatial scheme");
     if (time != HJ_RK1 && time != HJ_RK2 && time != HJ_RK3)
         return fail(HJ_E_ARG, "unknown RK order");

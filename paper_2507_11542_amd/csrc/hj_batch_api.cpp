@@ -381,7 +381,7 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
         }
     }
     if (g0->space == HJ_UPWIND1 || g0->order == 1)
-        return fail(HJ_E_UNSUPPORTED, "batched solves support ENO2/WENO5 with RK2/RK3");
+        return fail(HJ_E_UNSUPPORTED, "batched solves support ENO2, ENO3 and WENO5 with RK2/RK3");
     HJ_HIP(hipSetDevice(b->device), "hipSetDevice");
     if (b->pending) {
         HJ_HIP(hipEventSynchronize(b->done_evt), "previous batch");

@@ -213,6 +213,7 @@ hipError_t batch_launch_space(int space, const BatchPtrs<T> &p, uint32_t rounds,
                               const BatchShape &wg, hipStream_t s)
 {
     if (space == kEno2) return batch_launch_one<T, D, kEno2, DYN>(p, rounds, wg, s);
+    if (space == kEno3) return batch_launch_one<T, D, kEno3, DYN>(p, rounds, wg, s);
     if (space == kWeno5) return batch_launch_one<T, D, kWeno5, DYN>(p, rounds, wg, s);
     return hipErrorInvalidValue;
 }

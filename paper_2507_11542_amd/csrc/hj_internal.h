@@ -9,7 +9,7 @@ namespace hj {
 
 constexpr int kMaxDim = 4;
 
-enum Space { kUpwind1 = 1, kEno2 = 2, kWeno5 = 5 };
+enum Space { kUpwind1 = 1, kEno2 = 2, kEno3 = 3, kWeno5 = 5 };
 enum Dyn {
     kTranslation = 0,
     kBall = 1,
@@ -41,6 +41,7 @@ struct StageArgs {
     T dx[kMaxDim];
     T inv_dx[kMaxDim];   // 1/dx (FP64 on the host, then rounded to T)
     T inv_2dx[kMaxDim];  // 1/(2 dx)
+    T inv_3dx[kMaxDim];  // 1/(3 dx)
     T alpha[kMaxDim];
     T prm[8];
     T dt, wb, w2, den;

@@ -23,6 +23,8 @@ hipError_t launch_space(int space, const StageArgs<T> &a, hipStream_t s)
         if (space == kUpwind1) return launch_one<T, D, kUpwind1, DYN>(a, s);
     if constexpr ((SPACES >> kEno2) & 1u)
         if (space == kEno2) return launch_one<T, D, kEno2, DYN>(a, s);
+    if constexpr ((SPACES >> kEno3) & 1u)
+        if (space == kEno3) return launch_one<T, D, kEno3, DYN>(a, s);
     if constexpr ((SPACES >> kWeno5) & 1u)
         if (space == kWeno5) return launch_one<T, D, kWeno5, DYN>(a, s);
     return hipErrorInvalidValue;
@@ -64,7 +66,8 @@ hipError_t launch_stage_t(int ndim, int space, int dyn, const StageArgs<T> &a, h
     return hipErrorInvalidValue;
 }
 
-constexpr unsigned kAllSpaces = (1u << kUpwind1) | (1u << kEno2) | (1u << kWeno5);
+constexpr unsigned kAllSpaces =
+    (1u << kUpwind1) | (1u << kEno2) | (1u << kEno3) | (1u << kWeno5);
 
 
 }  // namespace hj

@@ -42,6 +42,8 @@ struct Halo<kUpwind1> { static constexpr int w = 1; };
 template <>
 struct Halo<kEno2> { static constexpr int w = 2; };
 template <>
+struct Halo<kEno3> { static constexpr int w = 3; };
+template <>
 struct Halo<kWeno5> { static constexpr int w = 3; };
 
 // Jiang-Peng WENO5 (Sec. 3.3; Osher-Fedkiw eqs. 3.28-3.39) on a window of
@@ -153,11 +155,11 @@ __device__ inline T line_value(const gmem<T> *__restrict__ v, uint32_t node, int
 
 // p- and p+ along one axis at one node (Sec. 3.1-3.3).
 // First divided differences use the reciprocal cell size 1/dx, second ones
-// 1/(2 dx) (both computed once on the host in FP64).
+// 1/(2 dx), third ones 1/(3 dx) (all computed once on the host in FP64).
 template <typename T, int SCH>
 __device__ inline void axis_derivs(const gmem<T> *__restrict__ v, uint32_t node, int i, int n,
                                    uint32_t stride, bool periodic, T dx, T inv_dx, T inv_2dx,
-                                   T &pm, T &pp, T &center)
+                                   T inv_3dx, T &pm, T &pp, T &center)
 {
     constexpr int W = Halo<SCH>::w;
     T s[2 * W + 1];
@@ -183,6 +185,39 @@ __device__ inline void axis_derivs(const gmem<T> *__restrict__ v, uint32_t node,
         for (int k = 0; k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) * inv_2dx;
         pm = d1[1] + dx * eno_pick(d2[0], d2[1]);
         pp = d1[2] - dx * eno_pick(d2[1], d2[2]);
+    } else if constexpr (SCH == kEno3) {
+        // HJ ENO3 (Osher-Fedkiw Sec. 3.3): d1[j] = D1 at i-5/2+j, d2[j] = D2
+        // at i-2+j, d3[j] = D3 at i-3/2+j; p = (Q1' + Q2') + Q3' with
+        // Q2' = +-c dx and Q3' = c* (2 or -1) dx^2 by where the stencil grew.
+        T d1[6], d2[5], d3[4];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) d1[k] = (s[k + 1] - s[k]) * inv_dx;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) d2[k] = (d1[k + 1] - d1[k]) * inv_2dx;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d3[k] = (d2[k + 1] - d2[k]) * inv_3dx;
+        const T dxx = dx * dx;
+        T c, cs, f;
+        if (fabs(d2[1]) <= fabs(d2[2])) {
+            c = d2[1];
+            cs = eno_pick(d3[0], d3[1]);
+            f = T(2);
+        } else {
+            c = d2[2];
+            cs = eno_pick(d3[1], d3[2]);
+            f = T(-1);
+        }
+        pm = (d1[2] + c * dx) + cs * (f * dxx);
+        if (fabs(d2[2]) <= fabs(d2[3])) {
+            c = d2[2];
+            cs = eno_pick(d3[1], d3[2]);
+            f = T(-1);
+        } else {
+            c = d2[3];
+            cs = eno_pick(d3[2], d3[3]);
+            f = T(2);
+        }
+        pp = (d1[3] - c * dx) + cs * (f * dxx);
     } else {
         T d1[6];
 #pragma unroll
@@ -258,8 +293,8 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
 #pragma unroll
     for (int d = 0; d < D; ++d)
         axis_derivs<T, SCH>(global_ptr(a.vs), node, ii[d], int(a.n[d]), a.stride[d],
-                            (a.periodic >> d) & 1u, a.dx[d], a.inv_dx[d], a.inv_2dx[d], pm[d],
-                            pp[d], center);
+                            (a.periodic >> d) & 1u, a.dx[d], a.inv_dx[d], a.inv_2dx[d],
+                            a.inv_3dx[d], pm[d], pp[d], center);
     T pbar[D];
     T diss = T(0);
 #pragma unroll

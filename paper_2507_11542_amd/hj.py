@@ -20,12 +20,12 @@ HJ_OK, HJ_E_ARG, HJ_E_OOM, HJ_E_DEVICE, HJ_E_STATE, HJ_E_NUMERIC, HJ_E_UNSUPPORT
     0, -1, -2, -3, -4, -5, -6
 HJ_FP64, HJ_FP32 = 0, 1
 HJ_SET, HJ_TUBE, HJ_TUBE_VI, HJ_TUBE_OUTPUTS = 0, 1, 2, 3
-HJ_UPWIND1, HJ_ENO2, HJ_WENO5 = 1, 2, 5
+HJ_UPWIND1, HJ_ENO2, HJ_ENO3, HJ_WENO5 = 1, 2, 3, 5
 HJ_RK1, HJ_RK2, HJ_RK3 = 1, 2, 3
 HJ_DYN_TRANSLATION, HJ_DYN_BALL, HJ_DYN_DOUBLE_INTEGRATOR, HJ_DYN_REL_DUBINS, \
     HJ_DYN_DUBINS4D, HJ_DYN_ROCKETS = 0, 1, 2, 3, 4, 5
 
-SPACE = {"upwind1": HJ_UPWIND1, "eno2": HJ_ENO2, "weno5": HJ_WENO5}
+SPACE = {"upwind1": HJ_UPWIND1, "eno2": HJ_ENO2, "eno3": HJ_ENO3, "weno5": HJ_WENO5}
 DYN = {"translation": HJ_DYN_TRANSLATION, "ball": HJ_DYN_BALL,
        "double_integrator": HJ_DYN_DOUBLE_INTEGRATOR, "rel_dubins": HJ_DYN_REL_DUBINS,
        "dubins4d": HJ_DYN_DUBINS4D, "rockets": HJ_DYN_ROCKETS}

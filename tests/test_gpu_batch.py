@@ -135,14 +135,18 @@ def test_flat_graph_reuse_and_recapture():
 
 
 def test_batch_other_dynamics_and_rk2(orc):
-    """4-D Dubins (set) and double-integrator ENO2/RK2 batches against the oracle."""
+    """4-D Dubins (set), double-integrator ENO2/RK2 and relative-Dubins ENO3
+    batches against the oracle."""
     from gpu_util import oracle_solve
 
     d4 = [inputs.dubins4d(n=(11, 13, 9, 12), w_max=0.7, tf=0.3),
           inputs.dubins4d(n=(15, 11, 10, 9), a_max=1.3, tf=0.5)]
     di = [inputs.double_integrator_2d(n=51, u_max=0.8, tf=0.5),
           inputs.double_integrator_2d(n=77, tf=1.0)]
-    for probs, shape in ((d4, SHAPES[0]), (di, SHAPES[0]), (d4, SHAPES[2]), (di, SHAPES[2])):
+    eno3 = [inputs.rel_dubins_3d(n=(21, 17, 16), tf=0.2, scheme="eno3"),
+            inputs.rel_dubins_3d(n=(15, 19, 12), tf=0.3, scheme="eno3").with_(mode="tube_vi")]
+    for probs, shape in ((d4, SHAPES[0]), (di, SHAPES[0]), (d4, SHAPES[2]), (di, SHAPES[2]),
+                         (eno3, SHAPES[0])):
         got, _, _ = _run_batch(probs, "fp64", **shape)
         for p, g in zip(probs, got):
             ref, *_ = oracle_solve(orc, p)

@@ -36,7 +36,8 @@ def _small_problems():
     out.append(("double_integrator_101", inputs.double_integrator_2d()))
     out.append(("rel_dubins_41x37x40", inputs.rel_dubins_3d(n=(41, 37, 40), tf=0.4)))
     out.append(("dubins4d_21x19x16x13", inputs.dubins4d(n=(21, 19, 16, 13), tf=0.25)))
-    for sch, order in (("upwind1", 1), ("eno2", 2), ("weno5", 3), ("weno5", 1), ("eno2", 3)):
+    for sch, order in (("upwind1", 1), ("eno2", 2), ("weno5", 3), ("weno5", 1), ("eno2", 3),
+                       ("eno3", 3), ("eno3", 2)):
         out.append(("rel_dubins_%s_rk%d" % (sch, order),
                     inputs.rel_dubins_3d(n=(23, 29, 18), tf=0.2, scheme=sch, order=order)))
     for nd, n in ((1, (301,)), (2, (67, 45)), (3, (19, 23, 21)), (4, (11, 13, 9, 10))):
@@ -78,7 +79,7 @@ def test_schedule_matches_oracle(orc, name, p):
     assert dt == rdt and k == rk
 
 
-@pytest.mark.parametrize("scheme", ["upwind1", "eno2", "weno5"])
+@pytest.mark.parametrize("scheme", ["upwind1", "eno2", "eno3", "weno5"])
 @pytest.mark.parametrize("dyn", ["rel_dubins", "dubins4d", "double_integrator"])
 def test_rhs_matches_oracle_on_rough_data(orc, scheme, dyn):
     """L(V) = -Hhat at every node for a rough seeded field (derivatives,
