@@ -17,6 +17,8 @@ Functions and the paper passages they follow:
                 global steps of the rockets game)
 - ``shapes``    implicit-surface initial values and their Boolean
                 combinations (Sec. 2.2, Fig. 4)
+- ``set_dissipation`` Lax-Friedrichs coefficients from the control sets (LF),
+                the node's costate box (LLF) or the grid-wide one (GLF) (Sec. 4)
 
 Every function is pinned by a ``-m "not gpu"`` test against closed forms,
 invariants, polynomial reproduction, convergence order or brute force; the
@@ -44,6 +46,7 @@ DYNAMICS = {"translation": 0, "ball": 1, "double_integrator": 2,
 MODES = {"set": 0, "tube": 1, "tube_vi": 2, "tube_out": 3}
 SHAPES = {"sphere": 0, "cylinder": 1, "box": 2, "ellipsoid": 3}
 OPS = {"union": 0, "intersect": 1, "subtract": 2}
+DISSIPATION = {"lf": 0, "llf": 1, "glf": 2}
 
 _lib = None
 
@@ -84,6 +87,10 @@ def _load():
     lib.orc_solve_outputs.restype = L
     lib.orc_shapes.argtypes = [I, P, P, P, U, I, P, P, P, P, P, P, P]
     lib.orc_shapes.restype = I
+    lib.orc_box_bound.argtypes = [I, P, P, P, U, I, P, I, L, I, P, P]
+    lib.orc_box_bound.restype = D
+    lib.orc_set_dissipation.argtypes = [I]
+    lib.orc_set_dissipation.restype = I
     lib.orc_set_threads.argtypes = [I]
     lib.orc_set_threads.restype = I
     _lib = lib
@@ -110,6 +117,29 @@ def _params(params):
     params = list(params)
     p[: len(params)] = params
     return p, len(params)
+
+
+def box_bound(n, lo, hi, periodic, dynamics, params, node, axis, blo, bhi) -> float:
+    """max over p in the costate box [blo, bhi] of |dH/dp_axis| at one node
+    (the LLF/GLF coefficient of Sec. 4)."""
+    lib = _load()
+    n, lo, hi, mask = _grid_args(n, lo, hi, periodic)
+    p, npar = _params(params)
+    bl = np.zeros(4)
+    bh = np.zeros(4)
+    bl[: len(blo)] = blo
+    bh[: len(bhi)] = bhi
+    return float(lib.orc_box_bound(len(n), _ptr(n), _ptr(lo), _ptr(hi), mask,
+                                   DYNAMICS[dynamics], _ptr(p), npar, int(node), int(axis),
+                                   _ptr(bl), _ptr(bh)))
+
+
+def set_dissipation(kind: str = "lf") -> str:
+    """Dissipation coefficients of later calls (Sec. 4): "lf" the control-set
+    bound (default), "llf" per node over its own costate box, "glf" per node
+    over the grid-wide box; returns the previous kind."""
+    old = int(_load().orc_set_dissipation(DISSIPATION[kind]))
+    return {v: k for k, v in DISSIPATION.items()}[old]
 
 
 def set_threads(n: int = 0) -> int:

@@ -16,6 +16,9 @@
  *       ENO3 (third divided differences, the c* choice)  [Sec. 3.2, ENO3 paragraph]
  *       WENO5 (Jiang-Peng weights)                       [Sec. 3.3]
  *   - Lax-Friedrichs numerical Hamiltonian               [Sec. 4, LF equation]
+ *     with the dissipation coefficients of reading R4 (LF), or per node over
+ *     the node's own costate box (LLF) or the grid-wide box (GLF)
+ *                                                        [Sec. 4, dissFunc(dL, dR)]
  *   - dissipation alpha_i = max over nodes of |dH/dp_i| bound, CFL dt [Sec. 4]
  *   - TVD Runge-Kutta 1/2/3 and the CFL time loop        [Sec. 5, odeCFL3 listing]
  *   - tube update V <- min(V, V0) after each step        [Sec. 6.1 BRT]
@@ -36,6 +39,15 @@
  *       p- = D1_{i-1/2} + dx*m(D2_{i-1}, D2_i), p+ = D1_{i+1/2} - dx*m(D2_i, D2_{i+1}),
  *       m(a,b) = a if |a| <= |b| else b (the <= tie rule printed for ENO3).
  *   R3  WENO5: Jiang-Peng with eps = 1e-6*max(v_k^2) + 1e-99.
+ *   R25 dissipation variants: alpha_d(x) = max over p in a costate box B and
+ *       over the controls of |dH/dp_d(x, p)|, with B the node's own
+ *       [min(p-, p+), max(p-, p+)] per axis (LLF) or the same over the whole
+ *       grid and both one-sided derivatives (GLF, the box of the dissFunc
+ *       (dL, dR) arguments); a switching function s = a.p (+ const) may take
+ *       the sign +1 where its interval's upper end is >= 0 and -1 where its
+ *       lower end is <= 0 (interval ends in axis order); the step size keeps
+ *       the control-set bound of R4, which bounds every box value, so the
+ *       schedule stays independent of V.
  *   R24 ENO3 (Osher-Fedkiw's HJ ENO3, which the paper follows):
  *       D3_{j+1/2} = (D2_{j+1} - D2_j)/(3dx) (with the reciprocal 1/(3dx));
  *       k = i-1 for p-, k = i for p+; Q1' = D1_{k+1/2};
@@ -86,6 +98,11 @@ enum { ORC_UPWIND1 = 1, ORC_ENO2 = 2, ORC_ENO3 = 3, ORC_WENO5 = 5 };
 enum { ORC_TRANSLATION = 0, ORC_BALL = 1, ORC_DOUBLE_INTEGRATOR = 2,
        ORC_REL_DUBINS = 3, ORC_DUBINS4D = 4, ORC_ROCKETS = 5 };
 enum { ORC_SET = 0, ORC_TUBE = 1, ORC_TUBE_VI = 2, ORC_TUBE_OUT = 3 };
+enum { ORC_LF = 0, ORC_LLF = 1, ORC_GLF = 2 };
+
+/* dissipation variant of the solver entry points (reading R25); set with
+ * orc_set_dissipation before a call */
+static int g_diss = ORC_LF;
 
 typedef struct {
     int nd;
@@ -456,6 +473,115 @@ static double speed_bound(const ogrid *g, const odyn *dy, long node, int d)
     return 0.0;
 }
 
+/* Reading R25: the interval of s = sum_j a_j p_j over the box lo..hi (axes
+ * in order), and the signs s may take there. */
+static void lin_interval(int nd, const double *a, const double *lo, const double *hi,
+                         double *smin, double *smax)
+{
+    double l = 0.0, h = 0.0;
+    for (int j = 0; j < nd; ++j) {
+        double u = a[j] * lo[j], w = a[j] * hi[j];
+        l = l + (u < w ? u : w);
+        h = h + (u < w ? w : u);
+    }
+    *smin = l;
+    *smax = h;
+}
+
+/* max over sign choices of |base + k * sigma| with sigma in the signs the
+ * interval [smin, smax] allows */
+static double sign_max(double base, double k, double smin, double smax)
+{
+    double m = 0.0;
+    if (smax >= 0.0) {
+        double v = fabs(base + k);
+        if (v > m) m = v;
+    }
+    if (smin <= 0.0) {
+        double v = fabs(base - k);
+        if (v > m) m = v;
+    }
+    return m;
+}
+
+/* Reading R25: max over p in the box lo..hi of |dH/dp_d| at one node. */
+static double box_bound(const ogrid *g, const odyn *dy, long node, int d, const double *lo,
+                        const double *hi)
+{
+    int nd = g->nd;
+    switch (dy->kind) {
+    case ORC_BALL: {
+        /* H = s|p|: |dH/dp_d| = |s| |p_d| / |p|, largest at the largest |p_d|
+         * and the smallest |p_j| (j != d) of the box */
+        double big = fabs(lo[d]) > fabs(hi[d]) ? fabs(lo[d]) : fabs(hi[d]);
+        double rest = 0.0;
+        int all_zero = big == 0.0;
+        for (int j = 0; j < nd; ++j) {
+            if (j == d) continue;
+            double m = (lo[j] <= 0.0 && hi[j] >= 0.0) ? 0.0
+                       : (fabs(lo[j]) < fabs(hi[j]) ? fabs(lo[j]) : fabs(hi[j]));
+            if (m != 0.0) all_zero = 0;
+            rest = rest + m * m;
+        }
+        if (big == 0.0) return all_zero ? fabs(dy->prm[0]) : 0.0;
+        return fabs(dy->prm[0]) * (big / sqrt(big * big + rest));
+    }
+    case ORC_REL_DUBINS: {
+        double ve = dy->prm[0], vp = dy->prm[1], we = dy->prm[2], wp = dy->prm[3];
+        double x = g->x[0][axis_index(g, node, 0)];
+        double y = g->x[1][axis_index(g, node, 1)];
+        long k = axis_index(g, node, 2);
+        double a[3] = {y, -x, -1.0}, smin, smax;
+        lin_interval(3, a, lo, hi, &smin, &smax);
+        /* dH/dp1 = (ve - vp cos) - we y sgn s, dH/dp2 = -vp sin + we x sgn s,
+         * dH/dp3 = we sgn s + wp sgn p3 */
+        if (d == 0) return sign_max(ve - vp * g->cs[2][k], -we * y, smin, smax);
+        if (d == 1) return sign_max(-(vp * g->sn[2][k]), we * x, smin, smax);
+        {
+            double m = 0.0;
+            if (smax >= 0.0) {
+                double v = sign_max(we, wp, lo[2], hi[2]);
+                if (v > m) m = v;
+            }
+            if (smin <= 0.0) {
+                double v = sign_max(-we, wp, lo[2], hi[2]);
+                if (v > m) m = v;
+            }
+            return m;
+        }
+    }
+    case ORC_ROCKETS: {
+        double am = dy->prm[0], grav = dy->prm[1], um = dy->prm[2];
+        double x = g->x[0][axis_index(g, node, 0)];
+        long k = axis_index(g, node, 2);
+        double a1[3] = {x, 0.0, -1.0}, a2[3] = {0.0, x, 1.0};
+        double l1, h1, l2, h2;
+        lin_interval(3, a1, lo, hi, &l1, &h1);
+        lin_interval(3, a2, lo, hi, &l2, &h2);
+        /* dH/dp1 = -a cos - um x sgn s1, dH/dp2 = -(a sin + a - g) + um x sgn s2,
+         * dH/dp3 = um sgn s1 - um sgn s2 */
+        if (d == 0) return sign_max(-(am * g->cs[2][k]), -um * x, l1, h1);
+        if (d == 1) return sign_max(-(am * g->sn[2][k] + am - grav), um * x, l2, h2);
+        {
+            double m = 0.0;
+            if (h1 >= 0.0) {
+                double v = sign_max(um, um, l2, h2);
+                if (v > m) m = v;
+            }
+            if (l1 <= 0.0) {
+                double v = sign_max(-um, um, l2, h2);
+                if (v > m) m = v;
+            }
+            return m;
+        }
+    }
+    default:
+        /* translation, double integrator, 4-D Dubins: |dH/dp_d| does not
+         * depend on p beyond the control bound */
+        return speed_bound(g, dy, node, d);
+    }
+}
+
 /* Sec. 4: global Lax-Friedrichs dissipation coefficients. */
 static void compute_alpha(const ogrid *g, const odyn *dy, double *alpha)
 {
@@ -484,17 +610,48 @@ static double cfl_dt(const ogrid *g, const double *alpha, double cfl)
  * (the dissipation summed over the axes in order, then subtracted) and the
  * semi-discrete right-hand side L(V) = -Hhat (from V_t + H = 0). */
 static double rhs_at(const ogrid *g, const odyn *dy, int scheme,
-                     const double *alpha, const double *v, long node)
+                     const double *alpha, const double *v, long node, const double *gbox)
 {
     double pm[ORC_MAXD], pp[ORC_MAXD], pbar[ORC_MAXD];
+    for (int d = 0; d < g->nd; ++d) derivs_at(g, v, node, d, scheme, &pm[d], &pp[d]);
+    /* reading R25: the costate box of the dissipation coefficients */
+    double lo[ORC_MAXD], hi[ORC_MAXD];
+    for (int d = 0; d < g->nd; ++d) {
+        if (g_diss == ORC_GLF) {
+            lo[d] = gbox[2 * d];
+            hi[d] = gbox[2 * d + 1];
+        } else {
+            lo[d] = pm[d] < pp[d] ? pm[d] : pp[d];
+            hi[d] = pm[d] < pp[d] ? pp[d] : pm[d];
+        }
+    }
     double diss = 0.0;
     for (int d = 0; d < g->nd; ++d) {
-        derivs_at(g, v, node, d, scheme, &pm[d], &pp[d]);
+        double a = g_diss == ORC_LF ? alpha[d] : box_bound(g, dy, node, d, lo, hi);
         pbar[d] = (pp[d] + pm[d]) / 2.0;
-        diss += alpha[d] * ((pp[d] - pm[d]) / 2.0);
+        diss += a * ((pp[d] - pm[d]) / 2.0);
     }
     double hhat = hamiltonian(g, dy, node, pbar) - diss;
     return -hhat;
+}
+
+/* Reading R25, GLF: the grid-wide box of both one-sided derivatives, per axis
+ * [min, max] into box[2d], box[2d+1]. */
+static void global_box(const ogrid *g, int scheme, const double *v, double *box)
+{
+    for (int d = 0; d < g->nd; ++d) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (long node = 0; node < g->total; ++node) {
+            double pm, pp;
+            derivs_at(g, v, node, d, scheme, &pm, &pp);
+            if (pm < lo) lo = pm;
+            if (pp < lo) lo = pp;
+            if (pm > hi) hi = pm;
+            if (pp > hi) hi = pp;
+        }
+        box[2 * d] = lo;
+        box[2 * d + 1] = hi;
+    }
 }
 
 /* L(V) at every node; in the variational-inequality tube (reading R21) the
@@ -502,9 +659,11 @@ static double rhs_at(const ogrid *g, const odyn *dy, int scheme,
 static void rhs_all(const ogrid *g, const odyn *dy, int scheme,
                     const double *alpha, const double *v, double *out, int mode)
 {
+    double box[2 * ORC_MAXD] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (g_diss == ORC_GLF) global_box(g, scheme, v, box);
 #pragma omp parallel for schedule(static)
     for (long node = 0; node < g->total; ++node) {
-        double l = rhs_at(g, dy, scheme, alpha, v, node);
+        double l = rhs_at(g, dy, scheme, alpha, v, node, box);
         if (mode == ORC_TUBE_VI && l > 0.0) l = 0.0;
         out[node] = l;
     }
@@ -623,8 +782,10 @@ int orc_rhs_at(int nd, const long *n, const double *lo, const double *hi,
         grid_free(&g);
         return -1;
     }
+    double box[2 * ORC_MAXD] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (g_diss == ORC_GLF) global_box(&g, scheme, v, box);
     for (long k = 0; k < count; ++k)
-        out[k] = rhs_at(&g, &dy, scheme, alpha, v, nodes[k]);
+        out[k] = rhs_at(&g, &dy, scheme, alpha, v, nodes[k], box);
     grid_free(&g);
     return 0;
 }
@@ -851,6 +1012,32 @@ int orc_shapes(int nd, const long *n, const double *lo, const double *hi,
     }
     grid_free(&g);
     return 0;
+}
+
+/* Reading R25 at one node: max over p in the box blo..bhi of |dH/dp_d|. */
+double orc_box_bound(int nd, const long *n, const double *lo, const double *hi,
+                     unsigned pmask, int dyn, const double *prm, int nprm, long node, int d,
+                     const double *blo, const double *bhi)
+{
+    ogrid g;
+    odyn dy;
+    memset(&g, 0, sizeof(g));
+    if (setup(&g, &dy, nd, n, lo, hi, pmask, dyn, prm, nprm) != 0) {
+        grid_free(&g);
+        return -1.0;
+    }
+    double r = box_bound(&g, &dy, node, d, blo, bhi);
+    grid_free(&g);
+    return r;
+}
+
+/* dissipation variant of later calls (reading R25): 0 LF, 1 LLF, 2 GLF;
+ * returns the previous one */
+int orc_set_dissipation(int kind)
+{
+    int old = g_diss;
+    g_diss = kind;
+    return old;
 }
 
 /* number of host threads used by the node loops (0 or less: all cores) */

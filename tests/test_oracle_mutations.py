@@ -19,8 +19,8 @@ MUTATIONS = {
                                   "*pm = (vp - vc) * inv_dx;\n        *pp = (vc - vm) * inv_dx;"),
     "eno2_right_correction_sign": ("*pp = d1[2] - dx * eno_pick", "*pp = d1[2] + dx * eno_pick"),
     "eno2_picks_larger": ("return fabs(a) <= fabs(b) ? a : b;", "return fabs(a) <= fabs(b) ? b : a;"),
-    "eno2_second_difference_scale": ("(d1[k + 1] - d1[k]) * g->inv_2dx[d]",
-                                     "(d1[k + 1] - d1[k]) * inv_dx"),
+    "eno2_second_difference_scale": ("k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) * g->inv_2dx[d]",
+                                     "k < 3; ++k) d2[k] = (d1[k + 1] - d1[k]) * inv_dx"),
     "weno_linear_weights_swapped": ("double a1 = 0.1 * r1, a2 = 0.6 * r2, a3 = 0.3 * r3;",
                                     "double a1 = 0.3 * r1, a2 = 0.6 * r2, a3 = 0.1 * r3;"),
     "weno_candidate_coefficient": ("v3 * C11_6", "v3 * C5_6"),
@@ -28,7 +28,8 @@ MUTATIONS = {
     "weno_right_weights_order": ("w[4], w[3], w[2], w[1], w[0], r.rc, r.rb, r.ra",
                                  "w[4], w[3], w[2], w[1], w[0], r.ra, r.rb, r.rc"),
     "weno_right_stencil_order": ("*pp = weno_right(&d1[1]);", "*pp = weno_left(&d1[1]);"),
-    "lf_dissipation_sign": ("diss += alpha[d] *", "diss -= alpha[d] *"),
+    "lf_dissipation_sign": ("diss += a * ((pp[d] - pm[d]) / 2.0);",
+                            "diss -= a * ((pp[d] - pm[d]) / 2.0);"),
     "rhs_sign": ("    return -hhat;\n}", "    return hhat;\n}"),
     "rk2_combination": ("v[k] = (v[k] + v2) / 2.0;", "v[k] = v2;"),
     "rk3_middle_stage": ("w2[k] = (3.0 * v[k] + v2) / 4.0;", "w2[k] = (v[k] + v2) / 2.0;"),
@@ -65,6 +66,13 @@ MUTATIONS = {
                                     "d3[k] = (d2[k + 1] - d2[k]) * g->inv_2dx[d];"),
     "eno3_right_first_difference": ("*pp = (d1[3] - c * dx) + cs * (f * dxx);",
                                     "*pp = (d1[2] - c * dx) + cs * (f * dxx);"),
+    "box_sign_minus_never": ("    if (smin <= 0.0) {\n        double v = fabs(base - k);",
+                             "    if (smin < -1e300) {\n        double v = fabs(base - k);"),
+    "box_interval_ends_swapped": ("l = l + (u < w ? u : w);", "l = l + (u < w ? w : u);"),
+    "glf_box_misses_right_derivative": ("            if (pp < lo) lo = pp;\n", ""),
+    "llf_box_upper_from_left_only": ("hi[d] = pm[d] < pp[d] ? pp[d] : pm[d];", "hi[d] = pm[d];"),
+    "rockets_box_p3_sign": ("double v = sign_max(-um, um, l2, h2);",
+                            "double v = sign_max(-um, -um, l2, h2);"),
     "box_inside_term_dropped": ("return sqrt(outside) + (inside < 0.0 ? inside : 0.0);",
                                 "return sqrt(outside);"),
     "ellipsoid_weight_outside_square": ("acc = acc + size[d] * (t * t);",
@@ -74,7 +82,8 @@ MUTATIONS = {
     "subtract_sign": ("v = -sv > v ? -sv : v;", "v = sv > v ? sv : v;"),
 }
 
-PIN_FILES = ("test_oracle_pins.py", "test_oracle_rockets_tubes.py", "test_oracle_shapes.py")
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_rockets_tubes.py", "test_oracle_shapes.py",
+             "test_oracle_dissipation.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
