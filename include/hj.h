@@ -64,6 +64,17 @@ typedef enum { HJ_SET = 0, HJ_TUBE = 1, HJ_TUBE_VI = 2, HJ_TUBE_OUTPUTS = 3 } hj
  * 3), WENO5 (Sec. 3.3, halo 3). */
 typedef enum { HJ_UPWIND1 = 1, HJ_ENO2 = 2, HJ_ENO3 = 3, HJ_WENO5 = 5 } hj_space;
 
+/* Lax-Friedrichs dissipation coefficients (Sec. 4; its dissipation routine
+ * takes the one-sided derivatives).  HJ_DISS_LF (default): alpha_d = max over
+ * the grid nodes of the control-set bound of |dH/dp_d|, once per solve.
+ * HJ_DISS_LLF: per node, max over the node's own costate box
+ * [min(p-, p+), max(p-, p+)] of |dH/dp_d|.  HJ_DISS_GLF: per node, max over
+ * the grid-wide box of both one-sided derivatives of the stage input (one
+ * extra reduction pass over the grid per stage).  A switching function's
+ * sign set over a box comes from interval arithmetic on its ends.  The step
+ * size always uses the control-set bound, which bounds both box variants. */
+typedef enum { HJ_DISS_LF = 0, HJ_DISS_LLF = 1, HJ_DISS_GLF = 2 } hj_dissipation;
+
 /* TVD Runge-Kutta order (Sec. 5): forward Euler, Shu-Osher RK2, RK3. */
 typedef enum { HJ_RK1 = 1, HJ_RK2 = 2, HJ_RK3 = 3 } hj_time;
 
@@ -142,6 +153,10 @@ hj_status hj_set_dynamics(hj_grid_t g, hj_dyn kind, const double *params, int np
 /* Sec. 3-5: derivative scheme, RK order and CFL number (0 < cfl <= 1).  The
  * default is WENO5, RK3, 0.8. */
 hj_status hj_set_scheme(hj_grid_t g, hj_space space, hj_time time, double cfl);
+
+/* Sec. 4: the dissipation coefficients of later solves and steps (see
+ * hj_dissipation).  HJ_E_ARG on an unknown kind. */
+hj_status hj_set_dissipation(hj_grid_t g, hj_dissipation kind);
 
 /* Sec. 5 time loop over [t0, tf] (odeCFL3): alpha is max-reduced on the GPU,
  * dt = cfl / sum_i alpha_i/dx_i, steps of min(dt, tf - t) until
@@ -238,8 +253,9 @@ hj_status hj_batch_config(hj_batch_t b, int tile_nodes, int workgroups, int use_
  * alpha reduction per instance (one synchronisation for all), then enqueues
  * the uploads and the launch on hip_stream and returns.  A second call waits
  * for the previous one of the same handle to finish before it reuses the
- * tables.  Modes HJ_SET, HJ_TUBE and HJ_TUBE_VI.  HJ_E_ARG on mismatched or
- * invalid instances, HJ_E_UNSUPPORTED for first-order schemes or RK1. */
+ * tables.  Modes HJ_SET, HJ_TUBE and HJ_TUBE_VI; dissipation HJ_DISS_LF or
+ * HJ_DISS_LLF per instance.  HJ_E_ARG on mismatched or invalid instances,
+ * HJ_E_UNSUPPORTED for first-order schemes, RK1 or HJ_DISS_GLF. */
 hj_status hj_solve_batch(hj_batch_t b, int n, const hj_grid_t *gs, const void *const *V0s,
                          void *const *Vouts, const double *t0, const double *tf,
                          const hj_mode *modes, void *hip_stream);

@@ -641,6 +641,8 @@ static void global_box(const ogrid *g, int scheme, const double *v, double *box)
 {
     for (int d = 0; d < g->nd; ++d) {
         double lo = INFINITY, hi = -INFINITY;
+        /* min and max are exact: any grouping of the nodes gives the same box */
+#pragma omp parallel for schedule(static) reduction(min : lo) reduction(max : hi)
         for (long node = 0; node < g->total; ++node) {
             double pm, pp;
             derivs_at(g, v, node, d, scheme, &pm, &pp);

@@ -166,6 +166,8 @@ StageArgs<T> base_args(hj_grid_t g)
     a.total = uint32_t(g->total);
     a.periodic = g->pmask;
     for (int k = 0; k < 8; ++k) a.prm[k] = T(g->prm[k]);
+    a.diss = g->diss;
+    a.box = (const T *)g->box_dev;
     return a;
 }
 template StageArgs<double> base_args<double>(hj_grid_t g);
@@ -178,9 +180,29 @@ namespace {
 template <typename T>
 hj_status launch(hj_grid_t g, const StageArgs<T> &a, hipStream_t s);
 
+// kGLF: the costate box of the stage input a.vs into g->box_dev, on the
+// stream before the stage.
+hj_status ensure_box(hj_grid_t g)
+{
+    hj_status s;
+    const size_t e = g->elem();
+    if (!g->box_dev && (s = dev_alloc(&g->box_dev, e * 2 * kMaxDim, "costate box")) != HJ_OK)
+        return s;
+    if (!g->box_part &&
+        (s = dev_alloc(&g->box_part, e * box_partial_values(uint32_t(g->total), g->nd),
+                       "costate box partials")) != HJ_OK)
+        return s;
+    return HJ_OK;
+}
+
 template <>
 hj_status launch<double>(hj_grid_t g, const StageArgs<double> &a, hipStream_t s)
 {
+    if (a.diss == kGLF) {
+        hipError_t e = launch_box_f64(g->nd, g->space, a, (double *)g->box_part,
+                                      (double *)g->box_dev, s);
+        if (e != hipSuccess) return hip_fail(e, "costate box (fp64)");
+    }
     hipError_t e = launch_stage_f64(g->nd, g->space, g->dyn, a, s);
     if (e != hipSuccess) return hip_fail(e, "stage launch (fp64)");
     return HJ_OK;
@@ -189,6 +211,11 @@ hj_status launch<double>(hj_grid_t g, const StageArgs<double> &a, hipStream_t s)
 template <>
 hj_status launch<float>(hj_grid_t g, const StageArgs<float> &a, hipStream_t s)
 {
+    if (a.diss == kGLF) {
+        hipError_t e = launch_box_f32(g->nd, g->space, a, (float *)g->box_part,
+                                      (float *)g->box_dev, s);
+        if (e != hipSuccess) return hip_fail(e, "costate box (fp32)");
+    }
     hipError_t e = launch_stage_f32(g->nd, g->space, g->dyn, a, s);
     if (e != hipSuccess) return hip_fail(e, "stage launch (fp32)");
     return HJ_OK;
@@ -209,6 +236,10 @@ hj_status stage(hj_grid_t g, const void *vs, const void *vb, const void *v0, voi
                 Combine c, double dt, double wb, double w2, double den, bool tube, bool vi,
                 hipStream_t s)
 {
+    if (g->diss == HJ_DISS_GLF) {
+        hj_status st = ensure_box(g);
+        if (st != HJ_OK) return st;
+    }
     StageArgs<T> a = base_args<T>(g);
     a.vs = (const T *)vs;
     a.vb = (const T *)vb;
@@ -403,6 +434,15 @@ hj_status hj_set_scheme(hj_grid_t g, hj_space space, hj_time time, double cfl)
     g->space = space;
     g->order = time;
     g->cfl = cfl;
+    return HJ_OK;
+}
+
+hj_status hj_set_dissipation(hj_grid_t g, hj_dissipation kind)
+{
+    if (!g) return fail(HJ_E_ARG, "null grid handle");
+    if (kind != HJ_DISS_LF && kind != HJ_DISS_LLF && kind != HJ_DISS_GLF)
+        return fail(HJ_E_ARG, "unknown dissipation kind");
+    g->diss = kind;
     return HJ_OK;
 }
 
@@ -629,6 +669,8 @@ hj_status hj_grid_destroy(hj_grid_t g)
     if (g->own_bufs && g->bufA) (void)hipFree(g->bufA);
     if (g->own_bufs && g->bufB) (void)hipFree(g->bufB);
     if (g->mixV) (void)hipFree(g->mixV);
+    if (g->box_dev) (void)hipFree(g->box_dev);
+    if (g->box_part) (void)hipFree(g->box_part);
     if (g->mixV0) (void)hipFree(g->mixV0);
     if (g->partial) (void)hipFree(g->partial);
     if (g->alpha_dev) (void)hipFree(g->alpha_dev);

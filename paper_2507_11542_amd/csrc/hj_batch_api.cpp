@@ -382,6 +382,11 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
     }
     if (g0->space == HJ_UPWIND1 || g0->order == 1)
         return fail(HJ_E_UNSUPPORTED, "batched solves support ENO2, ENO3 and WENO5 with RK2/RK3");
+    for (int i = 0; i < n; ++i)
+        if (gs[i]->diss == HJ_DISS_GLF)
+            return fail(HJ_E_UNSUPPORTED,
+                        "batched solves take HJ_DISS_LF or HJ_DISS_LLF (GLF needs a grid-wide "
+                        "reduction per stage)");
     HJ_HIP(hipSetDevice(b->device), "hipSetDevice");
     if (b->pending) {
         HJ_HIP(hipEventSynchronize(b->done_evt), "previous batch");

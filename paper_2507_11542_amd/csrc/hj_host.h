@@ -29,6 +29,10 @@ struct hj_grid_s {
     int space = HJ_WENO5;
     int order = 3;
     double cfl = 0.8;
+    int diss = HJ_DISS_LF;
+
+    void *box_dev = nullptr;   // kGLF: the costate box of the current stage input
+    void *box_part = nullptr;  // kGLF: its pass-1 partials
 
     double *tab64 = nullptr;   // device, FP64 tables (alpha and FP64 stages)
     float *tab32 = nullptr;    // device, FP32 tables (FP32 stages)

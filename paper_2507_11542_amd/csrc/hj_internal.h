@@ -19,6 +19,12 @@ enum Dyn {
     kRockets = 5
 };
 
+// Lax-Friedrichs coefficients: the per-solve control-set bound alpha (kLF), or
+// per node the max of |dH/dp_d| over a costate box: the node's own
+// [min(p-, p+), max(p-, p+)] (kLLF) or the grid-wide box of the stage input
+// (kGLF, reduced on the device before the stage).
+enum Diss { kLF = 0, kLLF = 1, kGLF = 2 };
+
 // How a stage kernel combines the right-hand side L(Vs) with its inputs:
 //   kRhs      out = L(Vs)
 //   kEuler    out = Vs + dt L(Vs)
@@ -48,6 +54,8 @@ struct StageArgs {
     int combine;
     int tube;         // out = min(out, v0[node])
     int vi;           // restricted update: L = min(L, 0) (variational-inequality tube)
+    int diss;         // Diss
+    const T *box;     // kGLF: [lo_0, hi_0, lo_1, hi_1, ...] on the device
 };
 
 struct AlphaArgs {
@@ -70,6 +78,15 @@ hipError_t launch_alpha(int ndim, int dyn, const AlphaArgs &a, double *partial, 
                         hipStream_t s);
 
 hipError_t launch_round_to_f32(const double *src, float *dst, uint32_t n, hipStream_t s);
+
+// Grid-wide costate box of a.vs (kGLF): box[2d], box[2d+1] = min, max over all
+// nodes of p- and p+ along axis d.  partial holds box_blocks(total) * 2 * ndim
+// values.
+uint32_t box_partial_values(uint32_t total, int ndim);
+hipError_t launch_box_f64(int ndim, int space, const StageArgs<double> &a, double *partial,
+                          double *box, hipStream_t s);
+hipError_t launch_box_f32(int ndim, int space, const StageArgs<float> &a, float *partial,
+                          float *box, hipStream_t s);
 
 // Implicit-surface initial values (the shapes of include/hj.h, evaluated in
 // FP64 and stored as double or float).

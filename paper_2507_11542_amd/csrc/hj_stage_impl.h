@@ -275,6 +275,127 @@ __device__ inline T hamiltonian(const StageArgs<T> &a, const int *ii, const T *p
     }
 }
 
+// Costate-box Lax-Friedrichs coefficients (the dissipation routine of Sec. 4
+// takes the one-sided derivatives): max over p in the box lo..hi and over
+// the controls of |dH/dp_d| at a node.  A switching function s = a.p has the
+// interval sum_j [min(a_j lo_j, a_j hi_j), max(..)] (axes in order) and may
+// take the sign +1 where its upper end is >= 0, -1 where its lower end is
+// <= 0.  Dynamics whose |dH/dp_d| does not depend on p give their control
+// bound.
+template <typename T>
+__device__ inline void lin_interval(const T *a, const T *lo, const T *hi, T *smin, T *smax)
+{
+    T l = T(0), h = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const T u = a[j] * lo[j], w = a[j] * hi[j];
+        l = l + (u < w ? u : w);
+        h = h + (u < w ? w : u);
+    }
+    *smin = l;
+    *smax = h;
+}
+
+// max over the signs the interval allows of |base + k sigma|
+template <typename T>
+__device__ inline T sign_max(T base, T k, T smin, T smax)
+{
+    T m = T(0);
+    if (smax >= T(0)) {
+        const T v = fabs(base + k);
+        if (v > m) m = v;
+    }
+    if (smin <= T(0)) {
+        const T v = fabs(base - k);
+        if (v > m) m = v;
+    }
+    return m;
+}
+
+template <typename T, int D, int DYN>
+__device__ inline T box_bound(const StageArgs<T> &a, const int *ii, int d, const T *lo,
+                              const T *hi)
+{
+    const gmem<T> *tab = global_ptr(a.tab);
+    if constexpr (DYN == kBall) {
+        const T big = fabs(lo[d]) > fabs(hi[d]) ? fabs(lo[d]) : fabs(hi[d]);
+        T rest = T(0);
+        bool all_zero = big == T(0);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j == d) continue;
+            const T m = (lo[j] <= T(0) && hi[j] >= T(0))
+                            ? T(0)
+                            : (fabs(lo[j]) < fabs(hi[j]) ? fabs(lo[j]) : fabs(hi[j]));
+            if (m != T(0)) all_zero = false;
+            rest = rest + m * m;
+        }
+        if (big == T(0)) return all_zero ? fabs(a.prm[0]) : T(0);
+        return fabs(a.prm[0]) * (big / sqrt(big * big + rest));
+    } else if constexpr (DYN == kRelDubins) {
+        const T ve = a.prm[0], vp = a.prm[1], we = a.prm[2], wp = a.prm[3];
+        const T x = tab[a.tab_off[0] + ii[0]];
+        const T y = tab[a.tab_off[1] + ii[1]];
+        const T coef[3] = {y, -x, T(-1)};
+        T smin, smax;
+        lin_interval(coef, lo, hi, &smin, &smax);
+        if (d == 0) {
+            const T c = tab[a.tab_off[2] + a.n[2] + ii[2]];
+            return sign_max(ve - vp * c, -we * y, smin, smax);
+        }
+        if (d == 1) {
+            const T s = tab[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+            return sign_max(-(vp * s), we * x, smin, smax);
+        }
+        T m = T(0);
+        if (smax >= T(0)) {
+            const T v = sign_max(we, wp, lo[2], hi[2]);
+            if (v > m) m = v;
+        }
+        if (smin <= T(0)) {
+            const T v = sign_max(-we, wp, lo[2], hi[2]);
+            if (v > m) m = v;
+        }
+        return m;
+    } else if constexpr (DYN == kRockets) {
+        const T am = a.prm[0], grav = a.prm[1], um = a.prm[2];
+        const T x = tab[a.tab_off[0] + ii[0]];
+        const T c1[3] = {x, T(0), T(-1)}, c2[3] = {T(0), x, T(1)};
+        T l1, h1, l2, h2;
+        lin_interval(c1, lo, hi, &l1, &h1);
+        lin_interval(c2, lo, hi, &l2, &h2);
+        if (d == 0) {
+            const T c = tab[a.tab_off[2] + a.n[2] + ii[2]];
+            return sign_max(-(am * c), -um * x, l1, h1);
+        }
+        if (d == 1) {
+            const T s = tab[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+            return sign_max(-(am * s + am - grav), um * x, l2, h2);
+        }
+        T m = T(0);
+        if (h1 >= T(0)) {
+            const T v = sign_max(um, um, l2, h2);
+            if (v > m) m = v;
+        }
+        if (l1 <= T(0)) {
+            const T v = sign_max(-um, um, l2, h2);
+            if (v > m) m = v;
+        }
+        return m;
+    } else if constexpr (DYN == kTranslation) {
+        return fabs(a.prm[d]);
+    } else if constexpr (DYN == kDoubleIntegrator) {
+        if (d == 0) return fabs(tab[a.tab_off[1] + ii[1]]);
+        return a.prm[0];
+    } else {
+        const T v = tab[a.tab_off[3] + ii[3]];
+        if (d == 0) return fabs(v * tab[a.tab_off[2] + a.n[2] + ii[2]]);
+        if (d == 1) return fabs(v * tab[a.tab_off[2] + 2 * a.n[2] + ii[2]]);
+        if (d == 2) return a.prm[0];
+        return a.prm[1];
+    }
+}
+
 // One node of one stage: derivatives along every axis, Lax-Friedrichs
 // right-hand side, RK combination and tube minimum; writes a.out[node].
 template <typename T, int D, int SCH, int DYN>
@@ -297,10 +418,29 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
                             a.inv_3dx[d], pm[d], pp[d], center);
     T pbar[D];
     T diss = T(0);
+    if (a.diss == kLF) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        pbar[d] = (pp[d] + pm[d]) * T(0.5);
-        diss += a.alpha[d] * ((pp[d] - pm[d]) * T(0.5));
+        for (int d = 0; d < D; ++d) {
+            pbar[d] = (pp[d] + pm[d]) * T(0.5);
+            diss += a.alpha[d] * ((pp[d] - pm[d]) * T(0.5));
+        }
+    } else {
+        T lo[D], hi[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (a.diss == kGLF) {
+                lo[d] = global_ptr(a.box)[2 * d];
+                hi[d] = global_ptr(a.box)[2 * d + 1];
+            } else {
+                lo[d] = pm[d] < pp[d] ? pm[d] : pp[d];
+                hi[d] = pm[d] < pp[d] ? pp[d] : pm[d];
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            pbar[d] = (pp[d] + pm[d]) * T(0.5);
+            diss += box_bound<T, D, DYN>(a, ii, d, lo, hi) * ((pp[d] - pm[d]) * T(0.5));
+        }
     }
     T l = -(hamiltonian<T, D, DYN>(a, ii, pbar) - diss);
     if (a.vi && l > T(0)) l = T(0);

@@ -33,6 +33,8 @@ MODE = {"set": HJ_SET, "tube": HJ_TUBE, "tube_vi": HJ_TUBE_VI, "tube_out": HJ_TU
 PREC = {"fp64": HJ_FP64, "fp32": HJ_FP32}
 
 SHAPE = {"sphere": 0, "cylinder": 1, "box": 2, "ellipsoid": 3}
+HJ_DISS_LF, HJ_DISS_LLF, HJ_DISS_GLF = 0, 1, 2
+DISSIPATION = {"lf": HJ_DISS_LF, "llf": HJ_DISS_LLF, "glf": HJ_DISS_GLF}
 OP = {"union": 0, "intersect": 1, "subtract": 2}
 
 
@@ -86,6 +88,7 @@ def _load():
     lib.hj_step.argtypes = [P, P, P, PD, D, I, PD, P]
     lib.hj_solve_mixed.argtypes = [P, P, P, D, D, I, D, P]
     lib.hj_solve_outputs.argtypes = [P, P, P, D, PD, I, I, P]
+    lib.hj_set_dissipation.argtypes = [P, I]
     lib.hj_init_shapes.argtypes = [P, P, P, I, P]
     lib.hj_rhs.argtypes = [P, P, P, P]
     lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
@@ -101,7 +104,7 @@ def _load():
     lib.hj_batch_wait.argtypes = [P, P, PD, PI64]
     lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
-                 "hj_solve_mixed", "hj_solve_outputs", "hj_init_shapes",
+                 "hj_solve_mixed", "hj_solve_outputs", "hj_init_shapes", "hj_set_dissipation",
                  "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_grid_set_workspace",
                  "hj_batch_create",
                  "hj_batch_config", "hj_solve_batch", "hj_step_batch", "hj_batch_wait",
@@ -175,6 +178,10 @@ def hj_set_scheme(g, space: int = HJ_WENO5, time: int = HJ_RK3, cfl: float = 0.8
 def hj_solve(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, stream=None):
     _check(_lib.hj_solve(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
                          _stream(stream)))
+
+
+def hj_set_dissipation(g, kind: int = HJ_DISS_LF):
+    _check(_lib.hj_set_dissipation(g, int(kind)))
 
 
 def hj_init_shapes(g, V_out, shape_list, stream=None):
@@ -330,6 +337,7 @@ class Grid:
         g = cls(p.n, p.lo, p.hi, p.periodic, prec)
         g.set_dynamics(p.dynamics, p.params)
         g.set_scheme(p.scheme, p.order, p.cfl)
+        g.set_dissipation(getattr(p, "diss", "lf"))
         return g
 
     def set_dynamics(self, name: str, params):
@@ -337,6 +345,9 @@ class Grid:
 
     def set_scheme(self, space="weno5", order=3, cfl=0.8):
         hj_set_scheme(self.handle, SPACE[space], int(order), cfl)
+
+    def set_dissipation(self, kind="lf"):
+        hj_set_dissipation(self.handle, DISSIPATION[kind])
 
     def solve(self, V0, V_out, t0, tf, mode="set", stream=None):
         hj_solve(self.handle, V0, V_out, t0, tf, MODE[mode], stream)

@@ -51,6 +51,7 @@ class Problem:
     mode: str = "tube"
     radius: float = 1.0          # V0 = sqrt(x0^2 + x1^2) - radius
     v0_axes: Tuple[int, ...] = (0, 1)
+    diss: str = "lf"             # Lax-Friedrichs coefficients: lf, llf, glf
 
     @property
     def ndim(self) -> int:

@@ -71,5 +71,9 @@ def gpu_rhs(p, v, prec="fp64"):
 
 def oracle_solve(orc, p, v0=None):
     v0 = p.v0() if v0 is None else v0
-    return orc.solve(v0, *p.grid_args(), p.dynamics, p.params, p.scheme, p.order, p.cfl,
-                     p.t0, p.tf, p.mode)
+    old = orc.set_dissipation(p.diss)
+    try:
+        return orc.solve(v0, *p.grid_args(), p.dynamics, p.params, p.scheme, p.order, p.cfl,
+                         p.t0, p.tf, p.mode)
+    finally:
+        orc.set_dissipation(old)
