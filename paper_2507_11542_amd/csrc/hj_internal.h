@@ -28,7 +28,7 @@ enum Diss { kLF = 0, kLLF = 1, kGLF = 2 };
 // How a stage kernel combines the right-hand side L(Vs) with its inputs:
 //   kRhs      out = L(Vs)
 //   kEuler    out = Vs + dt L(Vs)
-//   kBlend    out = (wb Vb + w2 (Vs + dt L(Vs))) / den
+//   kBlend    out = (wb Vb + w2 (Vs + dt L(Vs))) / den, den in {2, 3, 4}
 enum Combine { kRhs = 0, kEuler = 1, kBlend = 2 };
 
 // Everything one stage launch needs, by value (kernel argument).

@@ -450,17 +450,36 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
         val = l;
     } else {
         const T v2 = center + a.dt * l;
-        if (a.combine == kEuler)
+        if (a.combine == kEuler) {
             val = v2;
-        else
-            val = (a.wb * global_ptr(a.vb)[node] + a.w2 * v2) / a.den;
+        } else {
+            // the blends divide by 2, 4 (RK2, RK3 stage 2: the same as
+            // multiplying by 1/2, 1/4, exactly) or 3
+            const T x = a.wb * global_ptr(a.vb)[node] + a.w2 * v2;
+            val = a.den == T(3) ? x / T(3) : x * (a.den == T(4) ? T(0.25) : T(0.5));
+        }
     }
     if (a.tube) val = fmin(val, global_ptr(a.v0)[node]);
     global_ptr(a.out)[node] = val;
 }
 
+// Occupancy floor of the per-node kernel: the 3-D FP64 WENO5 kernels fit 80
+// VGPRs without spilling, which gives 6 waves per SIMD instead of 5;
+// elsewhere no floor (a floor of 6 makes the 3-D ENO3 and 4-D FP64 kernels
+// spill).
+template <typename T, int D, int SCH>
+struct StageWaves {
+    static constexpr int value = 1;
+};
+template <>
+struct StageWaves<double, 3, kWeno5> {
+    static constexpr int value = 6;
+};
+
 template <typename T, int D, int SCH, int DYN>
-__global__ __launch_bounds__(256) void stage_kernel(const StageArgs<T> a)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(StageWaves<T, D, SCH>::value))) void stage_kernel(
+    const StageArgs<T> a)
 {
     const uint32_t node = blockIdx.x * 256u + threadIdx.x;
     if (node >= a.total) return;
