@@ -157,6 +157,9 @@ StageArgs<T> base_args(hj_grid_t g)
         a.n[d] = uint32_t(g->n[d]);
         a.stride[d] = g->stride[d];
         a.tab_off[d] = g->tab_off[d];
+        const DivMagic mg = div_magic(uint32_t(g->n[d]));
+        a.nmul[d] = mg.m;
+        a.nshift[d] = mg.k;
         a.dx[d] = T(g->dx[d]);
         a.inv_dx[d] = T(1.0 / g->dx[d]);
         a.inv_2dx[d] = T(1.0 / (2.0 * g->dx[d]));

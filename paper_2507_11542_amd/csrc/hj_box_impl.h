@@ -85,12 +85,7 @@ __global__ __launch_bounds__(256) void box_partial(const StageArgs<T> a, T *part
     for (uint32_t node = blockIdx.x * 256u + threadIdx.x; node < a.total;
          node += gridDim.x * 256u) {
         int ii[D];
-        uint32_t r = node;
-#pragma unroll
-        for (int d = D - 1; d >= 0; --d) {
-            ii[d] = int(r % a.n[d]);
-            r /= a.n[d];
-        }
+        node_indices<T, D>(a, node, ii);
         T center;
 #pragma unroll
         for (int d = 0; d < D; ++d) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hj_divmagic.h"
+
 namespace hj {
 
 constexpr int kMaxDim = 4;
@@ -42,6 +44,8 @@ struct StageArgs {
     uint32_t n[kMaxDim];
     uint32_t stride[kMaxDim];
     uint32_t tab_off[kMaxDim];
+    uint32_t nmul[kMaxDim];    // floor(x / n[d]) = (x * nmul[d]) >> nshift[d]
+    uint32_t nshift[kMaxDim];
     uint32_t total;
     uint32_t periodic;  // bit d: axis d periodic
     T dx[kMaxDim];

@@ -35,6 +35,19 @@ __device__ inline gmem<T> *global_ptr(T *p)
     return (gmem<T> *)p;
 }
 
+// node index -> axis indices (C order) with the host's division magic
+template <typename T, int D>
+__device__ inline void node_indices(const StageArgs<T> &a, uint32_t node, int *ii)
+{
+    uint32_t r = node;
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) {
+        const uint32_t q = uint32_t((uint64_t(r) * a.nmul[d]) >> a.nshift[d]);
+        ii[d] = int(r - q * a.n[d]);
+        r = q;
+    }
+}
+
 template <int SCH>
 struct Halo;
 template <>
@@ -59,7 +72,7 @@ struct Halo<kWeno5> { static constexpr int w = 3; };
 // (rC, rB, rA) with the window reversed.
 //
 // FP64: every operation in the written order with correctly rounded
-// divisions, built without contraction, so each rounding equals that of a
+// divisions (div_rn_inrange below), built without contraction, so each rounding equals that of a
 // plain FP64 evaluation of the same formulas (the scheme amplifies rounding
 // differences by up to ~1e11 over a long horizon near the ridges of a game's
 // value function, so FP64 results are only comparable at 1e-12 when the
@@ -70,11 +83,40 @@ struct WenoR {
     T ra, rb, rc;
 };
 
+// FP64 division for the WENO weights: the fused-multiply-add divide sequence
+// (reciprocal estimate, two Newton steps, one residual correction) without
+// the range scaling and special-value fixup of the general divide.  Step for
+// step it is the general sequence in the case where that sequence does not
+// rescale, so it returns the correctly rounded quotient there: a nonzero
+// numerator and the denominator and quotient normal with exponents at least
+// 2^-970 and at most 2^1000 apart from overflow, or a zero numerator.  The
+// WENO denominators are (S + eps)^2 >= 1e-198 and sums of such weights, the
+// numerators 1 or weighted candidate sums, which stays inside that range for
+// any difference quotient of magnitude below 1e70.
+__device__ inline double div_rn_inrange(double a, double b)
+{
+    const double nb = -b;
+    const double r = __builtin_amdgcn_rcp(b);
+    const double y1 = fma(r, fma(nb, r, 1.0), r);
+    const double y2 = fma(y1, fma(nb, y1, 1.0), y1);
+    const double q = a * y2;
+    return fma(fma(nb, q, a), y2, q);
+}
+
+__device__ inline double rcp_rn_inrange(double b)
+{
+    const double nb = -b;
+    const double r = __builtin_amdgcn_rcp(b);
+    const double y1 = fma(r, fma(nb, r, 1.0), r);
+    const double y2 = fma(y1, fma(nb, y1, 1.0), y1);
+    return fma(fma(nb, y2, 1.0), y2, y2);
+}
+
 template <typename T>
 __device__ inline T wrecip(T x)
 {
     if constexpr (sizeof(T) == 8)
-        return T(1) / x;
+        return rcp_rn_inrange(x);
     else
         return __builtin_amdgcn_rcpf(x);
 }
@@ -120,7 +162,7 @@ __device__ inline T weno_blend(T v1, T v2, T v3, T v4, T v5, T r1, T r2, T r3)
     const T phi3 = v3 * c1_3 + v4 * c5_6 - v5 * c1_6;
     const T a1 = T(0.1) * r1, a2 = T(0.6) * r2, a3 = T(0.3) * r3;
     if constexpr (sizeof(T) == 8)
-        return (a1 * phi1 + a2 * phi2 + a3 * phi3) / (a1 + a2 + a3);
+        return div_rn_inrange(a1 * phi1 + a2 * phi2 + a3 * phi3, a1 + a2 + a3);
     else
         return (a1 * phi1 + a2 * phi2 + a3 * phi3) * wrecip(a1 + a2 + a3);
 }
@@ -402,14 +444,7 @@ template <typename T, int D, int SCH, int DYN>
 __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
 {
     int ii[D];
-    {
-        uint32_t r = node;
-#pragma unroll
-        for (int d = D - 1; d >= 0; --d) {
-            ii[d] = int(r % a.n[d]);
-            r /= a.n[d];
-        }
-    }
+    node_indices<T, D>(a, node, ii);
     T pm[D], pp[D], center = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d)
