@@ -195,18 +195,66 @@ __device__ inline T line_value(const gmem<T> *__restrict__ v, uint32_t node, int
     return e0 + T(j - (n - 1)) * (e0 - e1);
 }
 
+// The 2W+1 stencil values of the grid line through `node` around its axis
+// index i, ghosts included, without branches: every load uses a wrapped
+// (periodic) or clamped index, and the values beyond a bounded end are then
+// replaced by their linear extrapolations (the same formula as line_value).
+// Every lane of a wavefront runs the same instructions whether or not its node
+// is near an end; this suits the fastest axis, along which most wavefronts
+// hold some node near a line's end.
+template <typename T, int W>
+__device__ inline void line_stencil_select(const gmem<T> *__restrict__ v, uint32_t node, int i,
+                                           int n, uint32_t stride, bool periodic, T *s)
+{
+    const uint32_t base = node - uint32_t(i) * stride;
+    if (periodic) {
+#pragma unroll
+        for (int k = 0; k <= 2 * W; ++k) {
+            const int j = i - W + k;
+            const int jw = j < 0 ? j + n : (j >= n ? j - n : j);
+            s[k] = v[base + uint32_t(jw) * stride];
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k <= 2 * W; ++k) {
+        const int j = i - W + k;
+        const int jc = j < 0 ? 0 : (j >= n ? n - 1 : j);
+        s[k] = v[base + uint32_t(jc) * stride];
+    }
+    const T e0 = v[base], e1 = v[base + stride];
+    const T f0 = v[base + uint32_t(n - 1) * stride], f1 = v[base + uint32_t(n - 2) * stride];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int j = i - W + k;
+        const T g = e0 + T(-j) * (e0 - e1);
+        s[k] = j < 0 ? g : s[k];
+    }
+#pragma unroll
+    for (int k = W + 1; k <= 2 * W; ++k) {
+        const int j = i - W + k;
+        const T g = f0 + T(j - (n - 1)) * (f0 - f1);
+        s[k] = j >= n ? g : s[k];
+    }
+}
+
 // p- and p+ along one axis at one node (Sec. 3.1-3.3).
 // First divided differences use the reciprocal cell size 1/dx, second ones
 // 1/(2 dx), third ones 1/(3 dx) (all computed once on the host in FP64).
+// fastest: the axis is the last one (the stencil is gathered without
+// branches); on the other axes only the few wavefronts near an end take the
+// ghost path.
 template <typename T, int SCH>
 __device__ inline void axis_derivs(const gmem<T> *__restrict__ v, uint32_t node, int i, int n,
                                    uint32_t stride, bool periodic, T dx, T inv_dx, T inv_2dx,
-                                   T inv_3dx, T &pm, T &pp, T &center)
+                                   T inv_3dx, T &pm, T &pp, T &center, bool fastest = false)
 {
     constexpr int W = Halo<SCH>::w;
     T s[2 * W + 1];
     const bool interior = i >= W && i < n - W;
-    if (interior) {
+    if (fastest) {
+        line_stencil_select<T, W>(v, node, i, n, stride, periodic, s);
+    } else if (interior) {
 #pragma unroll
         for (int k = 0; k <= 2 * W; ++k) s[k] = v[node + (k - W) * int(stride)];
     } else {
@@ -450,7 +498,7 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
     for (int d = 0; d < D; ++d)
         axis_derivs<T, SCH>(global_ptr(a.vs), node, ii[d], int(a.n[d]), a.stride[d],
                             (a.periodic >> d) & 1u, a.dx[d], a.inv_dx[d], a.inv_2dx[d],
-                            a.inv_3dx[d], pm[d], pp[d], center);
+                            a.inv_3dx[d], pm[d], pp[d], center, d == D - 1);
     T pbar[D];
     T diss = T(0);
     if (a.diss == kLF) {
