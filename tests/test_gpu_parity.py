@@ -8,6 +8,7 @@ because the discrete scheme amplifies rounding differences by up to ~1e11
 over a long horizon.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -189,5 +190,19 @@ def test_full_size_rel_dubins_solve_samples():
     data = np.loadtxt(gold)
     idx = data[:, 0].astype(np.int64)
     p = inputs.rel_dubins_3d()
+    got = gpu_solve(p, "fp64").ravel()[idx]
+    assert np.abs(got - data[:, 1]).max() <= TOL64
+
+
+def test_full_size_dubins4d_solve_samples():
+    """The whole 61^4 4-D Dubins reachable set (182 steps, WENO5/LF/RK3,
+    FP64) at 4096 stored oracle nodes (tests/golden/make_dubins4d_samples.py
+    wrote them with the oracle alone)."""
+    from gpu_util import gpu_solve
+
+    gold = os.path.join(os.path.dirname(__file__), "golden", "dubins4d_61_set_samples.txt")
+    data = np.loadtxt(gold)
+    idx = data[:, 0].astype(np.int64)
+    p = inputs.dubins4d()
     got = gpu_solve(p, "fp64").ravel()[idx]
     assert np.abs(got - data[:, 1]).max() <= TOL64
