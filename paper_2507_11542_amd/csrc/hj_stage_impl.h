@@ -134,12 +134,10 @@ __device__ inline WenoR<T> weno_window(T w0, T w1, T w2, T w3, T w4)
     const T sa = c13_12 * ea * ea + T(0.25) * fa * fa;
     const T sb = c13_12 * eb * eb + T(0.25) * fb * fb;
     const T sc = c13_12 * ec * ec + T(0.25) * fc * fc;
-    T mx = w0 * w0;
-    mx = fmax(mx, w1 * w1);
-    mx = fmax(mx, w2 * w2);
-    mx = fmax(mx, w3 * w3);
-    mx = fmax(mx, w4 * w4);
-    const T eps = T(1e-6) * mx + (sizeof(T) == 8 ? T(1e-99) : T(1e-18));
+    // max_k w_k^2 as (max_k |w_k|)^2: rounding is monotone in |w|, so the
+    // rounded square of the largest magnitude is the largest rounded square
+    const T m = fmax(fmax(fmax(fmax(fabs(w0), fabs(w1)), fabs(w2)), fabs(w3)), fabs(w4));
+    const T eps = T(1e-6) * (m * m) + (sizeof(T) == 8 ? T(1e-99) : T(1e-18));
     WenoR<T> r;
     r.ra = wrecip((sa + eps) * (sa + eps));
     r.rb = wrecip((sb + eps) * (sb + eps));
@@ -309,14 +307,24 @@ __device__ inline void axis_derivs(const gmem<T> *__restrict__ v, uint32_t node,
         }
         pp = (d1[3] - c * dx) + cs * (f * dxx);
     } else {
+        // FP64: divided differences, as the formulas are written.  FP32: the
+        // undivided ones, scaled by 1/dx at the end (WENO5 is homogeneous of
+        // degree one in the differences; eps scales with them, its floor
+        // aside), which saves four multiplies per axis.
+        constexpr bool undivided = sizeof(T) == 4;
         T d1[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) d1[k] = (s[k + 1] - s[k]) * inv_dx;
+        for (int k = 0; k < 6; ++k)
+            d1[k] = undivided ? s[k + 1] - s[k] : (s[k + 1] - s[k]) * inv_dx;
         // p-: left-biased on the window d1[0..4]; p+: right-biased on d1[1..5]
         const WenoR<T> rl = weno_window(d1[0], d1[1], d1[2], d1[3], d1[4]);
         pm = weno_blend(d1[0], d1[1], d1[2], d1[3], d1[4], rl.ra, rl.rb, rl.rc);
         const WenoR<T> rr = weno_window(d1[1], d1[2], d1[3], d1[4], d1[5]);
         pp = weno_blend(d1[5], d1[4], d1[3], d1[2], d1[1], rr.rc, rr.rb, rr.ra);
+        if (undivided) {
+            pm *= inv_dx;
+            pp *= inv_dx;
+        }
     }
 }
 
