@@ -587,6 +587,8 @@ static void compute_alpha(const ogrid *g, const odyn *dy, double *alpha)
 {
     for (int d = 0; d < g->nd; ++d) {
         double m = 0.0;
+        /* a maximum is exact whatever the order, so the threads may split it */
+#pragma omp parallel for schedule(static) reduction(max : m)
         for (long node = 0; node < g->total; ++node) {
             double b = speed_bound(g, dy, node, d);
             if (b > m) m = b;
