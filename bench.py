@@ -254,7 +254,10 @@ def bench_served(args):
     (51^3..121^3) and 4-D Dubins (41^4..61^4) requests, WENO5+LF+RK3, FP32,
     horizons U[0.5,3]: served with continuous batching at several arrival
     rates (relative to the saturated completion rate) against the same
-    requests one at a time through hj_solve."""
+    requests one at a time through hj_solve.  By default both sides return
+    FP64 results with the tube minimum retaken in FP64 near the zero level
+    set (served: hj_tube_finish per finished request; plain: hj_solve_mixed).
+    """
     import numpy as np
 
     from paper_2507_11542_amd import inputs
@@ -262,15 +265,17 @@ def bench_served(args):
 
     n = args.serve_requests
     base = inputs.serving_stream(count=n, rate=1.0, seed=0)
+    v0_dtype = np.float64 if args.fp64_finish else np.float32
     v0_cache = ({} if args.device_v0 else
-                {k: r.problem.v0().astype(np.float32) for k, r in enumerate(base)})
+                {k: r.problem.v0().astype(v0_dtype) for k, r in enumerate(base)})
 
     def at_rate(rate):
         return [inputs.Request(r.arrival / rate, r.problem) for r in base]
 
     def served(rate):
         print("[bench] served at %.3g req/s" % rate, file=sys.stderr, flush=True)
-        be = GpuBackend(prec="fp32", v0_cache=v0_cache, device_v0=args.device_v0)
+        be = GpuBackend(prec="fp32", v0_cache=v0_cache, device_v0=args.device_v0,
+                        fp64_finish=args.fp64_finish)
         try:
             rep, _ = Server(be, hbm_budget=int(args.serve_budget_gib * (1 << 30)),
                             macro_steps=args.macro_steps,
@@ -282,7 +287,7 @@ def bench_served(args):
     def plain(rate):
         print("[bench] plain at %.3g req/s" % rate, file=sys.stderr, flush=True)
         rep, _ = run_plain(at_rate(rate), prec="fp32", v0_cache=v0_cache,
-                           device_v0=args.device_v0)
+                           device_v0=args.device_v0, fp64_finish=args.fp64_finish)
         return rep.as_dict()
 
     sat = served(1e9)  # everything arrives at once: saturated throughput
@@ -297,6 +302,8 @@ def bench_served(args):
             "macro_steps": args.macro_steps, "macro_updates": args.macro_updates,
             "v0": ("built on the GPU from each request's shape recipe (hj_init_shapes)"
                    if args.device_v0 else "uploaded from the host per request"),
+            "results": ("FP64: FP32 solve, tube minimum retaken in FP64 on |V| <= 3 max dx"
+                        if args.fp64_finish else "FP32"),
             "saturated_rate_req_per_s": lam_sat, "served": runs, "plain": plains,
             "served_vs_plain_updates_per_s":
                 sat["updates_per_s"] / plains["saturated"]["updates_per_s"]}
@@ -322,6 +329,9 @@ def main() -> int:
     ap.add_argument("--host-v0", dest="device_v0", action="store_false",
                     help="serving legs upload V0 from the host instead of building it on "
                          "the GPU from the request's shape recipe")
+    ap.add_argument("--fp32-results", dest="fp64_finish", action="store_false",
+                    help="serving legs return the FP32 solves as they are, without the "
+                         "FP64 tube finish")
     ap.add_argument("--macro-steps", type=int, default=64,
                     help="most RK steps per instance in one serving macro-iteration")
     ap.add_argument("--macro-updates", type=float, default=1.5e8,

@@ -198,6 +198,18 @@ hj_status hj_solve_outputs(hj_grid_t g, const void *V0, void *V_outs, double t0,
 hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0, double tf,
                          hj_mode mode, double band, void *hip_stream);
 
+/* The FP64 end of hj_solve_mixed on its own, for FP32 results computed some
+ * other way (hj_solve, hj_step, a batch): V_out = min(double(V32), V0) on the
+ * band |V32| <= band when mode is HJ_TUBE (the tube comparison of Sec. 6.1,
+ * taken in FP64 where the zero level set lies), double(V32) elsewhere and
+ * for HJ_SET and HJ_TUBE_VI.  V32 is the grid's FP32 array, V0 and V_out
+ * FP64 arrays of the grid's node count (device, C order); V_out must not
+ * overlap either.  band < 0 selects 3 max(dx).  hj_solve_mixed equals
+ * hj_solve on float(V0) followed by this call, bit for bit.  HJ_E_ARG on an
+ * FP64 grid, NULL pointers, overlap or another mode. */
+hj_status hj_tube_finish(hj_grid_t g, const float *V32, const double *V0, double *V_out,
+                         hj_mode mode, double band, void *hip_stream);
+
 /* One full TVD-RK step in place on V (device), of size min(dt, tf - *t),
  * then the tube update against V0 when mode is HJ_TUBE (V0 may be NULL for
  * HJ_SET and HJ_TUBE_VI; HJ_TUBE_OUTPUTS is not a per-step mode: HJ_E_ARG).  *t advances by the step (FP64, host); *dt_used receives it

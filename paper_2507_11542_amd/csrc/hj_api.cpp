@@ -314,6 +314,13 @@ bool overlap(const void *a, const void *b, size_t bytes)
     return x < y + bytes && y < x + bytes;
 }
 
+// [a, a + na) and [b, b + nb) share a byte
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = uintptr_t(a), y = uintptr_t(b);
+    return x < y + nb && y < x + na;
+}
+
 }  // namespace
 
 extern "C" {
@@ -585,11 +592,6 @@ hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0
         return fail(HJ_E_ARG, "need finite t0 <= tf");
     const size_t b64 = size_t(g->total) * sizeof(double);
     if (overlap(V0, V_out, b64)) return fail(HJ_E_ARG, "V_out overlaps V0");
-    if (band < 0.0) {
-        double m = 0.0;
-        for (int d = 0; d < g->nd; ++d) m = g->dx[d] > m ? g->dx[d] : m;
-        band = 3.0 * m;
-    }
     hipStream_t st = (hipStream_t)hip_stream;
     if ((s = use_device(g)) != HJ_OK) return s;
     if (!g->mixV && (s = dev_alloc(&g->mixV, g->bytes(), "mixed V")) != HJ_OK) return s;
@@ -597,8 +599,31 @@ hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0
     hipError_t e = launch_round_to_f32(V0, (float *)g->mixV0, uint32_t(g->total), st);
     if (e != hipSuccess) return hip_fail(e, "round to fp32");
     if ((s = hj_solve(g, g->mixV0, g->mixV, t0, tf, mode, hip_stream)) != HJ_OK) return s;
-    e = launch_finalize_f64((const float *)g->mixV, V0, V_out, uint32_t(g->total), band,
-                            mode == HJ_TUBE ? 1 : 0, st);
+    return hj_tube_finish(g, (const float *)g->mixV, V0, V_out, mode, band, hip_stream);
+}
+
+hj_status hj_tube_finish(hj_grid_t g, const float *V32, const double *V0, double *V_out,
+                         hj_mode mode, double band, void *hip_stream)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (g->prec != HJ_FP32) return fail(HJ_E_ARG, "hj_tube_finish needs an HJ_FP32 grid");
+    if (!V32 || !V0 || !V_out) return fail(HJ_E_ARG, "V32, V0 and V_out must be non-NULL");
+    if (mode != HJ_SET && mode != HJ_TUBE && mode != HJ_TUBE_VI)
+        return fail(HJ_E_ARG, "hj_tube_finish takes HJ_SET, HJ_TUBE or HJ_TUBE_VI");
+    if (!(band == band)) return fail(HJ_E_ARG, "band is NaN");
+    const size_t b64 = size_t(g->total) * sizeof(double);
+    if (overlap(V_out, b64, V32, g->bytes()) || overlap(V_out, b64, V0, b64))
+        return fail(HJ_E_ARG, "V_out overlaps V32 or V0");
+    if (band < 0.0) {
+        double m = 0.0;
+        for (int d = 0; d < g->nd; ++d) m = g->dx[d] > m ? g->dx[d] : m;
+        band = 3.0 * m;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = use_device(g)) != HJ_OK) return s;
+    hipError_t e = launch_finalize_f64(V32, V0, V_out, uint32_t(g->total), band,
+                                       mode == HJ_TUBE ? 1 : 0, st);
     if (e != hipSuccess) return hip_fail(e, "fp64 finalize");
     return HJ_OK;
 }

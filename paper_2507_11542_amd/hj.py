@@ -87,6 +87,7 @@ def _load():
     lib.hj_solve.argtypes = [P, P, P, D, D, I, P]
     lib.hj_step.argtypes = [P, P, P, PD, D, I, PD, P]
     lib.hj_solve_mixed.argtypes = [P, P, P, D, D, I, D, P]
+    lib.hj_tube_finish.argtypes = [P, P, P, P, I, D, P]
     lib.hj_solve_outputs.argtypes = [P, P, P, D, PD, I, I, P]
     lib.hj_set_dissipation.argtypes = [P, I]
     lib.hj_init_shapes.argtypes = [P, P, P, I, P]
@@ -104,8 +105,8 @@ def _load():
     lib.hj_batch_wait.argtypes = [P, P, PD, PI64]
     lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
-                 "hj_solve_mixed", "hj_solve_outputs", "hj_init_shapes", "hj_set_dissipation",
-                 "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_grid_set_workspace",
+                 "hj_solve_mixed", "hj_tube_finish", "hj_solve_outputs", "hj_init_shapes",
+                 "hj_set_dissipation", "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_grid_set_workspace",
                  "hj_batch_create",
                  "hj_batch_config", "hj_solve_batch", "hj_step_batch", "hj_batch_wait",
                  "hj_batch_destroy"):
@@ -201,6 +202,11 @@ def hj_solve_mixed(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, band:
                    stream=None):
     _check(_lib.hj_solve_mixed(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
                                float(band), _stream(stream)))
+
+
+def hj_tube_finish(g, V32, V0, V_out, mode: int = HJ_SET, band: float = -1.0, stream=None):
+    _check(_lib.hj_tube_finish(g, _ptr(V32), _ptr(V0), _ptr(V_out), int(mode), float(band),
+                               _stream(stream)))
 
 
 def hj_step(g, V, V0, t: float, tf: float, mode: int = HJ_SET, stream=None
@@ -366,6 +372,9 @@ class Grid:
 
     def solve_mixed(self, V0, V_out, t0, tf, mode="set", band=-1.0, stream=None):
         hj_solve_mixed(self.handle, V0, V_out, t0, tf, MODE[mode], band, stream)
+
+    def tube_finish(self, V32, V0, V_out, mode="set", band=-1.0, stream=None):
+        hj_tube_finish(self.handle, V32, V0, V_out, MODE[mode], band, stream)
 
     def rhs(self, V, L_out, stream=None):
         hj_rhs(self.handle, V, L_out, stream)

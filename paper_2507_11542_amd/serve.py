@@ -215,11 +215,16 @@ class GpuBackend:
     Every family has its own stream and engine; uploads of admitted requests
     go through a separate stream, so admitting never waits for a family's
     work in flight, and a family's next launch waits on the uploads of the
-    requests that joined it (stream-ordered events, no host wait)."""
+    requests that joined it (stream-ordered events, no host wait).
+
+    fp64_finish (FP32 only): each request also keeps its V0 in FP64, the FP32
+    working V0 is that rounded once, and a finished request's result is
+    widened to FP64 with the tube minimum retaken in FP64 near the zero level
+    set (hj_tube_finish), as hj_solve_mixed does for a single solve."""
 
     def __init__(self, prec: str = "fp32", tile_nodes: int = 256, workgroups: int = 0,
                  use_graph: bool = True, v0_cache: Optional[Dict[int, np.ndarray]] = None,
-                 device_v0: bool = False):
+                 device_v0: bool = False, fp64_finish: bool = False):
         import torch
 
         from . import hj
@@ -232,6 +237,9 @@ class GpuBackend:
         self.cfg = (tile_nodes, workgroups, use_graph)
         self.v0_cache = v0_cache if v0_cache is not None else {}
         self.device_v0 = device_v0  # build V0 from the problem's shape recipe on the GPU
+        if fp64_finish and prec != "fp32":
+            raise ValueError("fp64_finish needs prec='fp32'")
+        self.fp64_finish = fp64_finish
         self.engines: Dict[Tuple, object] = {}
         self.streams: Dict[Tuple, object] = {}
         self.events: Dict[Tuple, object] = {}
@@ -239,9 +247,11 @@ class GpuBackend:
         self.upload = torch.cuda.Stream(device=self.device)
 
     def bytes_needed(self, j: Job) -> int:
-        # V0, V and two stage buffers, plus the coordinate tables (FP64 and FP32)
+        # V0, V and two stage buffers, plus the coordinate tables (FP64 and FP32);
+        # with the FP64 finish also the FP64 V0 and result
         p = j.problem
-        return 4 * p.points * self.elem + sum(p.n) * 3 * (8 + 4) + 4096
+        extra = 16 * p.points if self.fp64_finish else 0
+        return 4 * p.points * self.elem + extra + sum(p.n) * 3 * (8 + 4) + 4096
 
     def _engine(self, key):
         if key not in self.engines:
@@ -253,27 +263,40 @@ class GpuBackend:
         torch = self.torch
         p = j.problem
         g = self.hj.Grid.from_problem(p, self.prec)
+        extra = {}
         try:
             with torch.cuda.stream(self.upload):
                 if self.device_v0:
                     v0 = torch.empty(tuple(p.n), dtype=self.dtype, device=self.device)
                     g.init_shapes(v0, p.shapes(), self.upload)
+                    if self.fp64_finish:  # the same recipe evaluated in FP64
+                        extra["v0_64"], extra["grid64"] = _device_v0_f64(self.hj, torch, p,
+                                                                         self.upload)
                 else:
                     v0h = self.v0_cache.get(j.rid)
                     if v0h is None:
                         v0h = p.v0()
-                    v0 = torch.from_numpy(np.ascontiguousarray(v0h)).to(
-                        self.device, self.dtype, non_blocking=False)
+                    host = torch.from_numpy(np.ascontiguousarray(v0h))
+                    v0 = host.to(self.device, self.dtype, non_blocking=False)
+                    if self.fp64_finish:
+                        extra["v0_64"] = host.to(self.device, torch.float64)
+                if self.fp64_finish:
+                    extra["out64"] = torch.empty_like(extra["v0_64"])
                 v = v0.clone()
                 a = torch.empty_like(v0)
                 b = torch.empty_like(v0)
+                if self.fp64_finish and p.tf <= p.t0:  # nothing to solve: finish V0
+                    g.tube_finish(v, extra["v0_64"], extra["out64"], p.mode, -1.0,
+                                  self.upload)
                 ready = torch.cuda.Event()
                 ready.record(self.upload)
         except RuntimeError as e:  # torch reports device OOM as RuntimeError
             g.close()
+            if "grid64" in extra:
+                extra["grid64"].close()
             raise MemoryError(str(e))
         g.set_workspace(a, b)
-        j.dev = {"grid": g, "v0": v0, "v": v, "a": a, "b": b, "ready": ready}
+        j.dev = {"grid": g, "v0": v0, "v": v, "a": a, "b": b, "ready": ready, **extra}
         j.t = p.t0
         j.dev_finished = p.tf <= p.t0
 
@@ -284,8 +307,9 @@ class GpuBackend:
             ev = j.dev.pop("ready", None)
             if ev is not None:  # first launch of a joined request: wait for its upload
                 stream.wait_event(ev)
-                for name in ("v0", "v", "a", "b"):
-                    j.dev[name].record_stream(stream)
+                for name in ("v0", "v", "a", "b", "v0_64", "out64"):
+                    if name in j.dev:
+                        j.dev[name].record_stream(stream)
         if todo:
             ts, taken, fin = eng.step([j.dev["grid"] for j in todo],
                                       [j.dev["v0"] for j in todo], [j.dev["v"] for j in todo],
@@ -296,6 +320,9 @@ class GpuBackend:
                 j.t = t
                 j.steps_done += k
                 j.dev_finished = f
+                if f and self.fp64_finish:
+                    j.dev["grid"].tube_finish(j.dev["v"], j.dev["v0_64"], j.dev["out64"],
+                                              j.problem.mode, -1.0, stream)
         ev = self.torch.cuda.Event()
         ev.record(stream)
         self.events[key] = ev
@@ -312,11 +339,26 @@ class GpuBackend:
     def idle(self, key):
         pass
 
+    @staticmethod
+    def _settle(j: Job):
+        # a request that never reached a family launch (empty horizon) still
+        # has its upload-stream work pending: wait for it before reading or
+        # freeing its buffers
+        ev = j.dev.get("ready")
+        if ev is not None:
+            ev.synchronize()
+
     def result(self, j: Job) -> np.ndarray:
+        self._settle(j)
+        if self.fp64_finish:
+            return j.dev["out64"].cpu().numpy()
         return j.dev["v"].double().cpu().numpy()
 
     def release(self, j: Job):
+        self._settle(j)
         j.dev["grid"].close()
+        if "grid64" in j.dev:
+            j.dev["grid64"].close()
         j.dev = None
 
     def close(self):
@@ -327,14 +369,29 @@ class GpuBackend:
         self.engines.clear()
 
 
+def _device_v0_f64(hj, torch, p, stream):
+    """V0 of problem p built on the device in FP64 from its shape recipe, and
+    the FP64 grid handle whose coordinate tables the kernel reads (to be
+    closed once the stream has passed it)."""
+    g64 = hj.Grid(p.n, p.lo, p.hi, p.periodic, "fp64")
+    try:
+        v0 = torch.empty(tuple(p.n), dtype=torch.float64, device="cuda")
+        g64.init_shapes(v0, p.shapes(), stream)
+    except BaseException:
+        g64.close()
+        raise
+    return v0, g64
+
+
 def run_plain(requests: Sequence[inputs.Request], prec: str = "fp32",
               v0_cache: Optional[Dict[int, np.ndarray]] = None, keep_results: bool = False,
-              device_v0: bool = False, clock=time.perf_counter, sleep=time.sleep
-              ) -> Tuple[ServeReport, List[Job]]:
+              device_v0: bool = False, clock=time.perf_counter, sleep=time.sleep,
+              fp64_finish: bool = False) -> Tuple[ServeReport, List[Job]]:
     """The same requests one at a time through hj_solve (no batching, no
     graph): each starts when it has arrived and the previous one finished.
     device_v0 builds V0 on the GPU from the problem's shape recipe, as the
-    serving backend can."""
+    serving backend can; fp64_finish solves through hj_solve_mixed (FP64 V0
+    and result, FP32 bulk), the single-solve form of the backend's option."""
     import torch
 
     from . import hj
@@ -352,20 +409,30 @@ def run_plain(requests: Sequence[inputs.Request], prec: str = "fp32",
             wait = j.arrival - (clock() - start)
         p = j.problem
         g = hj.Grid.from_problem(p, prec)
+        vdtype = torch.float64 if fp64_finish else dtype
+        g64 = None
         if device_v0:
-            v0 = torch.empty(tuple(p.n), dtype=dtype, device="cuda")
-            g.init_shapes(v0, p.shapes(), stream)
+            if fp64_finish:
+                v0, g64 = _device_v0_f64(hj, torch, p, stream)
+            else:
+                v0 = torch.empty(tuple(p.n), dtype=dtype, device="cuda")
+                g.init_shapes(v0, p.shapes(), stream)
         else:
             v0h = (v0_cache or {}).get(j.rid)
             v0 = torch.from_numpy(np.ascontiguousarray(v0h if v0h is not None else p.v0())).to(
-                "cuda", dtype)
+                "cuda", vdtype)
         out = torch.empty_like(v0)
         _, _, steps = g.schedule(p.t0, p.tf, stream)
-        g.solve(v0, out, p.t0, p.tf, p.mode, stream)
+        if fp64_finish:
+            g.solve_mixed(v0, out, p.t0, p.tf, p.mode, -1.0, stream)
+        else:
+            g.solve(v0, out, p.t0, p.tf, p.mode, stream)
         stream.synchronize()
         if keep_results:
             j.result = out.double().cpu().numpy()
         g.close()
+        if g64 is not None:
+            g64.close()
         j.state = "done"
         j.steps_done = steps
         j.finished_at = clock() - start

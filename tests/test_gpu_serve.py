@@ -64,3 +64,61 @@ def test_plain_path_reports():
     reqs = _stream(count=5, seed=11)
     rep, jobs = run_plain(reqs, prec="fp32")
     assert rep.completed == 5 and rep.updates > 0 and rep.p99_s >= rep.p50_s
+
+
+@pytest.mark.parametrize("device_v0", [False, True])
+def test_served_fp64_finish_equals_mixed_alone(device_v0):
+    """FP32 serving with the FP64 tube finish: every result (FP64) equals the
+    same request solved alone through hj_solve_mixed, bit for bit, including
+    a request with an empty horizon (finished at admission)."""
+    from paper_2507_11542_amd.serve import GpuBackend, Server, run_plain
+
+    reqs = _stream(count=9, seed=13)
+    first = reqs[0]
+    reqs.append(inputs.Request(first.arrival, first.problem.with_(tf=first.problem.t0)))
+    be = GpuBackend(prec="fp32", device_v0=device_v0, fp64_finish=True)
+    try:
+        rep, jobs = Server(be, hbm_budget=1 << 30, macro_steps=6).run(reqs, keep_results=True)
+    finally:
+        be.close()
+    assert rep.completed == len(reqs)
+    _, alone = run_plain(reqs, prec="fp32", keep_results=True, device_v0=device_v0,
+                         fp64_finish=True)
+    for j, a in zip(jobs, alone):
+        assert j.result.dtype == np.float64
+        assert np.array_equal(j.result, a.result), (j.rid, j.problem.name, j.problem.n)
+
+
+def test_tube_finish_equals_solve_mixed():
+    """hj_solve_mixed = hj_solve on float(V0) followed by hj_tube_finish, bit for
+    bit, for every mode and for the default and an explicit band."""
+    import torch
+
+    from paper_2507_11542_amd import hj
+
+    p = inputs.rel_dubins_3d(n=(23, 21, 18), tf=0.3)
+    st = torch.cuda.current_stream()
+    v0_64 = torch.from_numpy(p.v0()).to("cuda")
+    v0_32 = v0_64.float()
+    g = hj.Grid.from_problem(p, "fp32")
+    try:
+        for mode in ("tube", "set", "tube_vi"):
+            for band in (-1.0, 0.7):
+                mixed = torch.empty_like(v0_64)
+                g.solve_mixed(v0_64, mixed, p.t0, p.tf, mode, band, st)
+                v32 = torch.empty_like(v0_32)
+                g.solve(v0_32, v32, p.t0, p.tf, mode, st)
+                fin = torch.empty_like(v0_64)
+                g.tube_finish(v32, v0_64, fin, mode, band, st)
+                torch.cuda.synchronize()
+                assert torch.equal(fin, mixed), (mode, band)
+                if mode == "tube":
+                    m = v32.double()
+                    inside = m.abs() <= (band if band >= 0 else 3 * max(
+                        inputs.cell_sizes(*p.grid_args())))
+                    want = torch.where(inside, torch.minimum(m, v0_64), m)
+                    assert torch.equal(fin, want)
+        with pytest.raises(hj.HJError):  # V_out overlapping V0
+            g.tube_finish(v32, v0_64, v0_64, "tube", -1.0, st)
+    finally:
+        g.close()
