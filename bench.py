@@ -165,6 +165,61 @@ def bench_rockets(args):
     return res
 
 
+def bench_dubins4d(args):
+    """4-D Dubins car with speed state, 61^4 on [-5,5]^2 x [-pi,pi) x [0,4],
+    WENO5+LF+RK3, reachable set to t = 2 (182 steps), FP64 and FP32 side by
+    side: one hj_solve per repetition, V0 resident; both results against the
+    stored FP64 oracle values at 4096 seeded nodes, and FP32 against FP64."""
+    import numpy as np
+    import torch
+
+    from paper_2507_11542_amd import hj, inputs
+
+    p = inputs.dubins4d()
+    st = torch.cuda.current_stream()
+    gold = os.path.join(ROOT, "tests", "golden", "dubins4d_61_set_samples.txt")
+    data = np.loadtxt(gold) if os.path.exists(gold) else None
+    res = {"workload": "4-D Dubins 61^4 on [-5,5]^2 x [-pi,pi) x [0,4], |w|,|a| <= 1, "
+                       "WENO5+LF+RK3, reachable set to t=2"}
+    sampled = {}
+    for prec in ("fp64", "fp32"):
+        dtype = torch.float64 if prec == "fp64" else torch.float32
+        v0 = torch.from_numpy(p.v0()).to("cuda", dtype=dtype)
+        out = torch.empty_like(v0)
+        g = hj.Grid.from_problem(p, prec)
+        g.solve(v0, out, p.t0, p.tf, p.mode, st)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(args.rockets_reps):
+            t = time.perf_counter()
+            g.solve(v0, out, p.t0, p.tf, p.mode, st)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        steps = g.schedule(p.t0, p.tf, st)[2]
+        g.close()
+        row = {"solve_s": best, "steps": steps, "updates_per_s": p.points * steps / best}
+        if data is not None:
+            idx = torch.from_numpy(data[:, 0].astype(np.int64)).to("cuda")
+            vals = out.reshape(-1).index_select(0, idx).double().cpu().numpy()
+            sampled[prec] = vals
+            row["error_vs_oracle_fp64"] = float(np.abs(vals - data[:, 1]).max())
+            row["error_sampled_at"] = "%d stored oracle nodes (whole grid)" % len(data)
+        res[prec] = row
+        del v0, out
+    if len(sampled) == 2:
+        res["fp32_vs_fp64_max_abs"] = float(np.abs(sampled["fp32"] - sampled["fp64"]).max())
+        # stored nodes in the front band, 6 cells or more from a bounded edge
+        ii = np.unravel_index(data[:, 0].astype(np.int64), p.n)
+        keep = np.abs(data[:, 1]) < 3 * float(inputs.cell_sizes(*p.grid_args()).max())
+        for d, per in enumerate(p.periodic):
+            if not per:
+                keep &= (ii[d] >= 6) & (ii[d] < p.n[d] - 6)
+        res["fp32"]["band_error_vs_oracle_fp64"] = float(
+            np.abs(sampled["fp32"] - data[:, 1])[keep].max())
+        res["fp32"]["band_nodes_sampled"] = int(keep.sum())
+    return res
+
+
 def bench_batched(args):
     """64 relative-Dubins tubes of uneven size (N ~ U{51,61,81,101}, seeded
     speeds and turn bounds), FP32 with FP64 time: one batched solve (round
@@ -318,7 +373,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=40,
                     help="RK steps timed with HIP events for the kernel roofline")
-    ap.add_argument("--no-rockets", action="store_true")
+    ap.add_argument("--no-rockets", action="store_true",
+                    help="skip the rockets and 4-D Dubins legs")
     ap.add_argument("--rockets-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=64)
@@ -436,6 +492,9 @@ def main() -> int:
     if not args.no_rockets:
         print("[bench] rockets leg", file=sys.stderr, flush=True)
         rec["rockets"] = bench_rockets(args)
+    if not args.no_rockets:
+        print("[bench] 4-D leg", file=sys.stderr, flush=True)
+        rec["dubins4d"] = bench_dubins4d(args)
     if not args.no_batch:
         print("[bench] batched leg", file=sys.stderr, flush=True)
         rec["batched"] = bench_batched(args)

@@ -206,3 +206,31 @@ def test_full_size_dubins4d_solve_samples():
     p = inputs.dubins4d()
     got = gpu_solve(p, "fp64").ravel()[idx]
     assert np.abs(got - data[:, 1]).max() <= TOL64
+
+
+def test_full_size_dubins4d_fp32_side_by_side():
+    """The same 61^4 solve in FP32 beside the stored FP64 oracle values: the
+    stored nodes in the front band (|V| < 3 max dx, 6 cells from the bounded
+    edges) within 1e-4, every stored node within 5e-3."""
+    import json
+
+    from gpu_util import gpu_solve
+
+    gold = os.path.join(os.path.dirname(__file__), "golden", "dubins4d_61_set_samples.txt")
+    data = np.loadtxt(gold)
+    idx = data[:, 0].astype(np.int64)
+    p = inputs.dubins4d()
+    got = gpu_solve(p, "fp32").ravel()[idx]
+    err = np.abs(got - data[:, 1])
+    dx = inputs.cell_sizes(*p.grid_args())
+    ii = np.unravel_index(idx, p.n)
+    near_edge = np.zeros(idx.size, dtype=bool)
+    for d, per in enumerate(p.periodic):
+        if not per:
+            near_edge |= (ii[d] < 6) | (ii[d] >= p.n[d] - 6)
+    band = (np.abs(data[:, 1]) < 3 * dx.max()) & ~near_edge
+    print(json.dumps({"band_nodes": int(band.sum()), "band_err": float(err[band].max()),
+                      "all_err": float(err.max())}), flush=True)
+    assert band.sum() > 50
+    assert err[band].max() <= 1e-4
+    assert err.max() <= 5e-3
