@@ -567,12 +567,24 @@ struct StageWaves<double, 3, kWeno5> {
     static constexpr int value = 6;
 };
 
+// Tile of workgroup b out of nb.  Workgroups are dispatched to the chip's 8
+// XCDs round-robin (b on XCD b % 8), and each XCD has its own L2: XCD x takes
+// the x-th contiguous eighth of the tiles (the first nb % 8 eighths one tile
+// longer), so the stencil neighbours along the slow axes of the nodes an XCD
+// updates are mostly in tiles that the same XCD updates.  A bijection of
+// [0, nb) whatever the dispatch order, so correctness does not depend on it.
+__device__ inline uint32_t xcd_tile(uint32_t b, uint32_t nb)
+{
+    const uint32_t q = nb >> 3, r = nb & 7u, x = b & 7u, i = b >> 3;
+    return (x < r ? x * (q + 1u) : r * (q + 1u) + (x - r) * q) + i;
+}
+
 template <typename T, int D, int SCH, int DYN>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(StageWaves<T, D, SCH>::value))) void stage_kernel(
     const StageArgs<T> a)
 {
-    const uint32_t node = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t node = xcd_tile(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
     if (node >= a.total) return;
     stage_node<T, D, SCH, DYN>(a, node);
 }

@@ -220,11 +220,17 @@ class GpuBackend:
     fp64_finish (FP32 only): each request also keeps its V0 in FP64, the FP32
     working V0 is that rounded once, and a finished request's result is
     widened to FP64 with the tube minimum retaken in FP64 near the zero level
-    set (hj_tube_finish), as hj_solve_mixed does for a single solve."""
+    set (hj_tube_finish), as hj_solve_mixed does for a single solve.
+
+    solo_points: a request with at least this many nodes fills the chip with
+    its own launches, so its family advances it with its own hj_step calls
+    (the single-solve stage kernel) after the batched launch of the family's
+    smaller requests, on the same stream; None batches every request."""
 
     def __init__(self, prec: str = "fp32", tile_nodes: int = 256, workgroups: int = 0,
                  use_graph: bool = True, v0_cache: Optional[Dict[int, np.ndarray]] = None,
-                 device_v0: bool = False, fp64_finish: bool = False):
+                 device_v0: bool = False, fp64_finish: bool = False,
+                 solo_points: Optional[int] = 2_000_000):
         import torch
 
         from . import hj
@@ -240,6 +246,7 @@ class GpuBackend:
         if fp64_finish and prec != "fp32":
             raise ValueError("fp64_finish needs prec='fp32'")
         self.fp64_finish = fp64_finish
+        self.solo_points = solo_points
         self.engines: Dict[Tuple, object] = {}
         self.streams: Dict[Tuple, object] = {}
         self.events: Dict[Tuple, object] = {}
@@ -296,9 +303,14 @@ class GpuBackend:
                 extra["grid64"].close()
             raise MemoryError(str(e))
         g.set_workspace(a, b)
+        if self._solo(j):  # its step count (and alpha, cached in the handle)
+            extra["steps"] = g.schedule(p.t0, p.tf, self.upload)[2]
         j.dev = {"grid": g, "v0": v0, "v": v, "a": a, "b": b, "ready": ready, **extra}
         j.t = p.t0
         j.dev_finished = p.tf <= p.t0
+
+    def _solo(self, j: Job) -> bool:
+        return self.solo_points is not None and j.problem.points >= self.solo_points
 
     def advance(self, key, group: List[Job], max_steps: int):
         eng, stream = self._engine(key)
@@ -310,17 +322,33 @@ class GpuBackend:
                 for name in ("v0", "v", "a", "b", "v0_64", "out64"):
                     if name in j.dev:
                         j.dev[name].record_stream(stream)
-        if todo:
-            ts, taken, fin = eng.step([j.dev["grid"] for j in todo],
-                                      [j.dev["v0"] for j in todo], [j.dev["v"] for j in todo],
-                                      [j.problem.t0 for j in todo], [j.t for j in todo],
-                                      [j.problem.tf for j in todo],
-                                      [j.problem.mode for j in todo], max_steps, stream)
-            for j, t, k, f in zip(todo, ts, taken, fin):
+        batched = [j for j in todo if not self._solo(j)]
+        if batched:
+            ts, taken, fin = eng.step([j.dev["grid"] for j in batched],
+                                      [j.dev["v0"] for j in batched],
+                                      [j.dev["v"] for j in batched],
+                                      [j.problem.t0 for j in batched], [j.t for j in batched],
+                                      [j.problem.tf for j in batched],
+                                      [j.problem.mode for j in batched], max_steps, stream)
+            for j, t, k, f in zip(batched, ts, taken, fin):
                 j.t = t
                 j.steps_done += k
                 j.dev_finished = f
-                if f and self.fp64_finish:
+        for j in todo:
+            if not self._solo(j):
+                continue
+            # the same steps as hj_solve: its step count, each of
+            # min(dt, tf - t), t accumulated in FP64 on the host
+            k = min(max_steps, j.dev["steps"] - j.steps_done)
+            g, t = j.dev["grid"], j.t
+            for _ in range(k):
+                t, _ = g.step(j.dev["v"], j.dev["v0"], t, j.problem.tf, j.problem.mode, stream)
+            j.t = t
+            j.steps_done += k
+            j.dev_finished = j.steps_done >= j.dev["steps"]
+        if self.fp64_finish:
+            for j in todo:
+                if j.dev_finished:
                     j.dev["grid"].tube_finish(j.dev["v"], j.dev["v0_64"], j.dev["out64"],
                                               j.problem.mode, -1.0, stream)
         ev = self.torch.cuda.Event()

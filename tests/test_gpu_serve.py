@@ -66,17 +66,19 @@ def test_plain_path_reports():
     assert rep.completed == 5 and rep.updates > 0 and rep.p99_s >= rep.p50_s
 
 
-@pytest.mark.parametrize("device_v0", [False, True])
-def test_served_fp64_finish_equals_mixed_alone(device_v0):
+@pytest.mark.parametrize("device_v0,solo_points", [(False, None), (True, 5000)])
+def test_served_fp64_finish_equals_mixed_alone(device_v0, solo_points):
     """FP32 serving with the FP64 tube finish: every result (FP64) equals the
     same request solved alone through hj_solve_mixed, bit for bit, including
-    a request with an empty horizon (finished at admission)."""
+    a request with an empty horizon (finished at admission), with every
+    request batched or the larger ones stepped on their own."""
     from paper_2507_11542_amd.serve import GpuBackend, Server, run_plain
 
     reqs = _stream(count=9, seed=13)
     first = reqs[0]
     reqs.append(inputs.Request(first.arrival, first.problem.with_(tf=first.problem.t0)))
-    be = GpuBackend(prec="fp32", device_v0=device_v0, fp64_finish=True)
+    be = GpuBackend(prec="fp32", device_v0=device_v0, fp64_finish=True,
+                    solo_points=solo_points)
     try:
         rep, jobs = Server(be, hbm_budget=1 << 30, macro_steps=6).run(reqs, keep_results=True)
     finally:
@@ -122,3 +124,24 @@ def test_tube_finish_equals_solve_mixed():
             g.tube_finish(v32, v0_64, v0_64, "tube", -1.0, st)
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("solo_points", [1, 5000])
+def test_served_solo_requests_equal_alone(solo_points):
+    """Requests at or above solo_points nodes advance with their own hj_step
+    calls inside their family's step (all of them, or the larger ones beside
+    a batch of the smaller): every result equals hj_solve alone, bit for bit."""
+    from gpu_util import gpu_solve
+    from paper_2507_11542_amd.serve import GpuBackend, Server
+
+    reqs = _stream(count=12, seed=17)
+    sizes = [r.problem.points for r in reqs]
+    assert solo_points == 1 or min(sizes) < solo_points <= max(sizes)
+    be = GpuBackend(prec="fp32", solo_points=solo_points)
+    try:
+        rep, jobs = Server(be, hbm_budget=1 << 30, macro_steps=5).run(reqs, keep_results=True)
+    finally:
+        be.close()
+    assert rep.completed == len(reqs)
+    for j in jobs:
+        assert np.array_equal(j.result, gpu_solve(j.problem, "fp32")), (j.rid, j.problem.n)
