@@ -486,6 +486,9 @@ def main() -> int:
                      "kernel": "stage_kernel<%s,3,WENO5,REL_DUBINS>" % args.prec,
                      "launch_us": launch_s * 1e6,
                      "algorithmic_hbm_GBs": hbm_gbs,
+                     "measured_hbm_GBs": (measured_traffic(args.prec) / launch_s / 1e9
+                                          if measured_traffic(args.prec) else None),
+                     "hbm_peak_GBs": 8000.0,
                      "flops_per_node_stage": weno5_flops_per_node_stage(p.ndim)},
         "error_vs_oracle_fp64": err,
     }
