@@ -397,7 +397,7 @@ def main() -> int:
                          "the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only; multi-GPU runs are not part of this build "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(got --gpus %d)" % args.gpus, file=sys.stderr)
         return 2
 
