@@ -58,7 +58,7 @@ struct hj_batch_s {
     // captured graphs and the launches they were captured for
     struct Graph {
         hipGraphExec_t exec = nullptr;
-        int nd = -1, space = -1, dyn = -1, prec = -1;
+        int nd = -1, space = -1, dyn = -1, prec = -1, order = -1;
         uint32_t wg = 0, rounds = 0;
         std::vector<uint32_t> grid;  // flat: workgroups of each round
         uint64_t used = 0;           // last use (LRU)
@@ -186,8 +186,8 @@ uint32_t grid_capacity(uint32_t tiles)
 // whose per-round workgroups (flat launches) cover the batch's tiles of
 // every round, captured on demand (least recently used one dropped beyond
 // kMaxGraphs).  The round tables (h_round_off) are the batch's.
-hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, uint32_t rounds,
-              hipStream_t s)
+hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, int order,
+              uint32_t rounds, hipStream_t s)
 {
     const bool flat = b->workgroups == 0;
     std::vector<uint32_t> &grid = b->round_grid;
@@ -195,7 +195,7 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, uint3
     for (uint32_t r = 0; flat && r < rounds; ++r)
         grid[r] = b->h_round_off[r + 1] - b->h_round_off[r];
     if (!b->use_graph) {
-        const BatchShape sh{b->workgroups, grid.data()};
+        const BatchShape sh{b->workgroups, grid.data(), uint32_t(order)};
         hipError_t e = launch_any(b, nd, space, dyn, prec, rounds, sh, s);
         if (e != hipSuccess) return hip_fail(e, "batch launch");
         return HJ_OK;
@@ -203,7 +203,7 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, uint3
     hj_batch_s::Graph *hit = nullptr;
     for (auto &g : b->graphs) {
         if (g.nd != nd || g.space != space || g.dyn != dyn || g.prec != prec ||
-            g.wg != b->workgroups || g.rounds != rounds)
+            g.order != order || g.wg != b->workgroups || g.rounds != rounds)
             continue;
         bool fits = true;
         for (uint32_t r = 0; flat && r < rounds && fits; ++r) fits = grid[r] <= g.grid[r];
@@ -217,6 +217,7 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, uint3
         g.nd = nd;
         g.space = space;
         g.dyn = dyn;
+        g.order = order;
         g.prec = prec;
         g.wg = b->workgroups;
         g.rounds = rounds;
@@ -228,7 +229,7 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, uint3
         hipGraph_t graph = nullptr;
         HJ_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal),
                "begin capture");
-        const BatchShape sh{b->workgroups, g.grid.data()};
+        const BatchShape sh{b->workgroups, g.grid.data(), uint32_t(order)};
         hipError_t e = launch_any(b, nd, space, dyn, prec, rounds, sh, b->capture_stream);
         hipError_t e2 = hipStreamEndCapture(b->capture_stream, &graph);
         if (e != hipSuccess) {
@@ -485,7 +486,8 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
         for (int i = 0; i < n; ++i)
             HJ_HIP(hipMemcpyAsync(Vs[i], V0s[i], gs[i]->bytes(), hipMemcpyDeviceToDevice, st),
                    "copy V0");
-    if ((s = run(b, g0->nd, g0->space, g0->dyn, g0->prec, rounds, st)) != HJ_OK) return s;
+    if ((s = run(b, g0->nd, g0->space, g0->dyn, g0->prec, g0->order, rounds, st)) != HJ_OK)
+        return s;
     HJ_HIP(hipMemcpyAsync(b->h_ctl_out, b->ctl, sizeof(BatchCtl) * n, hipMemcpyDeviceToHost, st),
            "read-back");
     HJ_HIP(hipEventRecord(b->done_evt, st), "batch event");

@@ -74,14 +74,14 @@ __global__ __launch_bounds__(256) void batch_init(BatchPtrs<T> p)
     }
 }
 
-// Arguments of stage (r % order) of instance `inst` for round r, and the
-// step size h of that step (from the instance's device time t_n).
+// Arguments of stage `stage` of step `step` (round step * order + stage) of
+// instance `inst`, and the step size h of that step (from the instance's
+// device time t_n).
 template <typename T>
-__device__ inline StageArgs<T> batch_stage_args(const BatchPtrs<T> &p, uint32_t inst, uint32_t r,
+__device__ inline StageArgs<T> batch_stage_args(const BatchPtrs<T> &p, uint32_t inst,
+                                                uint32_t order, uint32_t stage, uint32_t step,
                                                 double *h_out, double *tn_out)
 {
-    const uint32_t order = p.gl->order;
-    const uint32_t stage = r % order, step = r / order;
     const BatchInst<T> &in = p.inst[inst];
     const double t_n = p.ctl[inst].t[step & 1u];
     const double rem = in.tf - t_n;
@@ -145,18 +145,19 @@ __device__ inline void batch_item(const BatchPtrs<T> &p, uint32_t local, uint32_
 // the strided form keep about twice the VGPRs live, halving occupancy);
 // workgroups beyond the round's tiles return at once.
 template <typename T, int D, int SCH, int DYN, bool FLAT>
-__global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r)
+__global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r, uint32_t order)
 {
     if (r >= p.gl->rounds) return;  // rounds beyond this batch: nothing to do
     const uint32_t begin = p.round_off[r], end = p.round_off[r + 1];
-    const uint32_t order = p.gl->order;
-    const uint32_t stage = r % order, step = r / order;
+    // the RK order is the launch's, so stage and step need no division here
+    const uint32_t stage = order == 3 ? r % 3u : (order == 2 ? r & 1u : 0u);
+    const uint32_t step = order == 3 ? r / 3u : (order == 2 ? r >> 1 : r);
     if (FLAT) {
         if (blockIdx.x >= end - begin) return;
         uint32_t inst, tile;
         batch_item(p, blockIdx.x, &inst, &tile);
         double h, t_n;
-        const StageArgs<T> a = batch_stage_args(p, inst, r, &h, &t_n);
+        const StageArgs<T> a = batch_stage_args(p, inst, order, stage, step, &h, &t_n);
         const uint32_t node = tile * 256u + threadIdx.x;
         if (node < a.total) stage_node<T, D, SCH, DYN>(a, node);
         // the other slot: read by no tile of this step
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r)
         uint32_t inst, tile;
         batch_item(p, k - begin, &inst, &tile);
         double h, t_n;
-        const StageArgs<T> a = batch_stage_args(p, inst, r, &h, &t_n);
+        const StageArgs<T> a = batch_stage_args(p, inst, order, stage, step, &h, &t_n);
         const uint32_t tn = p.inst[inst].tile_nodes;
         const uint32_t first = tile * tn;
         const uint32_t last = first + tn < a.total ? first + tn : a.total;
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r)
 struct BatchShape {
     uint32_t workgroups;
     const uint32_t *round_grid;  // host array [rounds], flat form only
+    uint32_t order;              // RK order of the batch (1, 2 or 3)
 };
 
 // The init kernel and rounds [0, rounds) of the round kernel, back to back.
@@ -192,16 +194,17 @@ template <typename T, int D, int SCH, int DYN>
 hipError_t batch_launch_one(const BatchPtrs<T> &p, uint32_t rounds, const BatchShape &sh,
                             hipStream_t s)
 {
+    const uint32_t order = sh.order;
     hipLaunchKernelGGL((batch_init<T>), dim3(1), dim3(256), 0, s, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (uint32_t r = 0; r < rounds; ++r) {
         if (sh.workgroups)
             hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, false>), dim3(sh.workgroups),
-                               dim3(256), 0, s, p, r);
+                               dim3(256), 0, s, p, r, order);
         else
             hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, true>), dim3(sh.round_grid[r]),
-                               dim3(256), 0, s, p, r);
+                               dim3(256), 0, s, p, r, order);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
