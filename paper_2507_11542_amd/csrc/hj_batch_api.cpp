@@ -160,6 +160,7 @@ BatchPtrs<T> ptrs(hj_batch_t b)
     p.tile_map = b->tile_map;
     p.round_off = b->round_off;
     p.gl = b->gl;
+    p.map_cap = b->cap_tiles;
     return p;
 }
 

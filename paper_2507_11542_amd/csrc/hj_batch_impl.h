@@ -62,6 +62,7 @@ struct BatchPtrs {
                                // count, descending; round r runs a prefix of it
     const uint32_t *round_off; // [rounds + 1] first work item of each round
     const BatchGlobal *gl;
+    uint32_t map_cap;          // entries allocated for tile_map (>= 1)
 };
 
 template <typename T>
@@ -147,15 +148,20 @@ __device__ inline void batch_item(const BatchPtrs<T> &p, uint32_t local, uint32_
 template <typename T, int D, int SCH, int DYN, bool FLAT>
 __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r, uint32_t order)
 {
-    if (r >= p.gl->rounds) return;  // rounds beyond this batch: nothing to do
+    // r < the batch's round count: rounds are launched for exactly the batch's
+    // rounds (a replayed graph was captured for the same round count)
+    const uint32_t b = blockIdx.x;
+    // the map entry is loaded beside the round bounds rather than after them
+    // (clamped into the map; used only by a workgroup that has a tile)
+    const TileRef t = p.tile_map[b < p.map_cap ? b : p.map_cap - 1u];
     const uint32_t begin = p.round_off[r], end = p.round_off[r + 1];
     // the RK order is the launch's, so stage and step need no division here
     const uint32_t stage = order == 3 ? r % 3u : (order == 2 ? r & 1u : 0u);
     const uint32_t step = order == 3 ? r / 3u : (order == 2 ? r >> 1 : r);
     if (FLAT) {
-        if (blockIdx.x >= end - begin) return;
-        uint32_t inst, tile;
-        batch_item(p, blockIdx.x, &inst, &tile);
+        if (b >= end - begin) return;
+        const uint32_t inst = __builtin_amdgcn_readfirstlane(t.inst);
+        const uint32_t tile = __builtin_amdgcn_readfirstlane(t.tile);
         double h, t_n;
         const StageArgs<T> a = batch_stage_args(p, inst, order, stage, step, &h, &t_n);
         const uint32_t node = tile * 256u + threadIdx.x;
