@@ -132,6 +132,43 @@ def test_edge_cases(orc):
     assert np.abs(gpu_solve(p) - ref).max() <= TOL64
 
 
+def test_zero_speed_single_step(orc):
+    """Zero speed (alpha = 0, unbounded CFL step): one step of tf - t0 that
+    leaves V0 unchanged, through hj_solve and through a batch, both
+    precisions, as the oracle."""
+    import torch
+
+    from gpu_util import gpu_solve, oracle_solve, to_dev
+    from paper_2507_11542_amd import hj
+
+    p = inputs.Problem("still", (19, 17), (-1.0, -1.0), (1.0, 1.0), (False, True), "ball",
+                       (0.0,), "weno5", 3, 0.8, 0.0, 0.7, "tube", radius=0.4)
+    ref, alpha, dt, k = oracle_solve(orc, p)
+    assert k == 1
+    v32 = p.v0().astype(np.float32)
+    for prec in ("fp64", "fp32"):
+        got = gpu_solve(p, prec)
+        if prec == "fp64":
+            assert np.array_equal(got, ref)
+        else:  # V0 up to the rounding of the RK3 combinations
+            assert np.all(np.abs(got - v32) <= 4 * np.spacing(np.abs(v32)))
+        g = hj.Grid.from_problem(p, prec)
+        _, gdt, steps = g.schedule(p.t0, p.tf, torch.cuda.current_stream())
+        assert np.isinf(gdt) and steps == 1
+        v0 = to_dev(p.v0(), prec)
+        out = torch.empty_like(v0)
+        b = hj.Batch()
+        try:
+            b.solve([g], [v0], [out], [p.t0], [p.tf], [p.mode], torch.cuda.current_stream())
+            tfin, _ = b.wait(1, torch.cuda.current_stream())
+            torch.cuda.synchronize()
+        finally:
+            b.close()
+            g.close()
+        assert tfin[0] == p.tf
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), got)
+
+
 def test_full_size_rel_dubins_steps(orc):
     """The 101^3 relative-Dubins grid in the launch configuration of the
     benchmark: two RK3 tube steps from V0, every node against the oracle."""

@@ -404,3 +404,18 @@ def test_dubins4d_heading_and_speed_terms(orc):
     ex = np.maximum(np.maximum(np.abs(TH) - T, 0) - 0.5, np.maximum(np.abs(V - 2.0) - T / 2, 0) - 0.5)
     assert metrics.hausdorff_cells(out, ex, per) < 0.6
     assert np.abs(out - ex)[np.abs(ex) < 0.2].max() < 0.06
+
+
+@pytest.mark.parametrize("dyn,params", [("translation", (0.0, 0.0)), ("ball", (0.0,))])
+def test_zero_speed_is_one_step_and_changes_nothing(orc, dyn, params):
+    """Dynamics with zero speed: alpha = 0, the CFL step is unbounded, so the
+    time loop takes the single step h = tf - t0, and L(V) = 0 leaves V0 as it
+    is (the LF dissipation vanishes with alpha) up to the rounding of the RK3
+    convex combinations (a few ulp)."""
+    n, lo, hi, per = (19, 17), (-1.0, -1.0), (1.0, 1.0), (False, True)
+    X, Y = np.meshgrid(*inputs.node_coords(n, lo, hi, per), indexing="ij")
+    v0 = np.ascontiguousarray(np.sin(3 * X) * np.cos(2 * np.pi * Y) + X * Y)
+    alpha, dt, k, tend = orc.schedule(n, lo, hi, per, dyn, params, 0.8, 0.0, 0.7)
+    assert np.all(alpha == 0.0) and np.isinf(dt) and k == 1 and tend == 0.7
+    out, *_ = orc.solve(v0, n, lo, hi, per, dyn, params, "weno5", 3, 0.8, 0.0, 0.7, "tube")
+    assert np.all(np.abs(out - v0) <= 4 * np.spacing(np.abs(v0)))
