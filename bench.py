@@ -345,6 +345,36 @@ def bench_served(args):
                            device_v0=args.device_v0, fp64_finish=args.fp64_finish)
         return rep.as_dict()
 
+    def accuracy():
+        """The smallest request of each family served again (all at once;
+        results do not depend on the mix) against the FP64 oracle's stored
+        values."""
+        gold = os.path.join(ROOT, "tests", "golden", "serving_stream_samples.txt")
+        if not os.path.exists(gold) or n != 96:
+            return None
+        rows = np.loadtxt(gold)
+        ids = sorted({int(k) for k in rows[:, 0]})
+        reqs = [inputs.Request(0.0, base[k].problem) for k in ids]
+        be = GpuBackend(prec="fp32", v0_cache={i: v0_cache[k] for i, k in enumerate(ids)}
+                        if v0_cache else None, device_v0=args.device_v0,
+                        fp64_finish=args.fp64_finish)
+        try:
+            _, jobs = Server(be, hbm_budget=int(args.serve_budget_gib * (1 << 30)),
+                             macro_steps=args.macro_steps,
+                             macro_updates=args.macro_updates).run(reqs, keep_results=True)
+        finally:
+            be.close()
+        out = {}
+        for k, j in zip(ids, jobs):
+            sel = rows[rows[:, 0] == k]
+            err = np.abs(j.result.ravel()[sel[:, 1].astype(np.int64)] - sel[:, 3])
+            band = sel[:, 2] == 1
+            out[j.problem.dynamics] = {
+                "request": k, "grid": list(j.problem.n), "horizon": j.problem.tf,
+                "band_max_abs": float(err[band].max()) if band.any() else None,
+                "sampled_max_abs": float(err.max())}
+        return out
+
     sat = served(1e9)  # everything arrives at once: saturated throughput
     lam_sat = sat["completed"] / sat["makespan_s"]
     runs = {"saturated": sat}
@@ -360,6 +390,7 @@ def bench_served(args):
             "results": ("FP64: FP32 solve, tube minimum retaken in FP64 on |V| <= 3 max dx"
                         if args.fp64_finish else "FP32"),
             "saturated_rate_req_per_s": lam_sat, "served": runs, "plain": plains,
+            "served_vs_oracle_fp64": accuracy(),
             "served_vs_plain_updates_per_s":
                 sat["updates_per_s"] / plains["saturated"]["updates_per_s"]}
 
