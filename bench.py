@@ -353,6 +353,13 @@ def bench_served(args):
         if not os.path.exists(gold) or n != 96:
             return None
         rows = np.loadtxt(gold)
+        spread = {}
+        with open(gold) as f:
+            for line in f:
+                w = line.split()
+                if line.startswith("# request") and "noise_spread" in w:
+                    spread[int(w[2])] = (float(w[w.index("storage_spread") + 1]),
+                                         float(w[w.index("noise_spread") + 1]))
         ids = sorted({int(k) for k in rows[:, 0]})
         reqs = [inputs.Request(0.0, base[k].problem) for k in ids]
         be = GpuBackend(prec="fp32", v0_cache={i: v0_cache[k] for i, k in enumerate(ids)}
@@ -372,7 +379,9 @@ def bench_served(args):
             out[j.problem.dynamics] = {
                 "request": k, "grid": list(j.problem.n), "horizon": j.problem.tf,
                 "band_max_abs": float(err[band].max()) if band.any() else None,
-                "sampled_max_abs": float(err.max())}
+                "sampled_max_abs": float(err.max()),
+                "oracle_storage_spread": spread.get(k, (None, None))[0],
+                "oracle_noise_spread": spread.get(k, (None, None))[1]}
         return out
 
     sat = served(1e9)  # everything arrives at once: saturated throughput

@@ -2,8 +2,11 @@
 each family in the 96-request serving stream (seed 0: a double integrator, a
 relative-Dubins tube and a 4-D Dubins set, WENO5/LF/RK3), the FP64 oracle's
 solution at up to 512 seeded front-band nodes (|V| < 3 max(dx), at least 6
-cells from a bounded edge) and 256 seeded nodes anywhere.  Calls only the
-oracle and the input generators.
+cells from a bounded edge) and 256 seeded nodes anywhere, and the oracle's own
+spread in that band when its state is rounded to FP32 after every step
+(storage) and also multiplied by (1 + 2^-23 z), z seeded normal, first
+(noise), as for the relative-Dubins batch.  Calls only the oracle and the
+input generators.
 
     python tests/golden/make_serving_samples.py
 """
@@ -32,6 +35,19 @@ def picked(base):
     return [best[f] for f in sorted(best)]
 
 
+def _stepped(p, alpha, dt, perturb):
+    """The oracle's time loop one step at a time, perturb applied after each."""
+    v0 = p.v0()
+    v = perturb(v0.copy())
+    t, eps = p.t0, 100.0 * 2.220446049250313e-16
+    while p.tf - t >= eps * (p.tf - p.t0):
+        h = dt if dt < p.tf - t else p.tf - t
+        v = perturb(oracle.steps(v, v0, *p.grid_args(), p.dynamics, p.params, p.scheme,
+                                 p.order, alpha, h, 1, mode=p.mode))
+        t = t + h
+    return v
+
+
 def main():
     oracle.set_threads(0)
     base = inputs.serving_stream(count=96, rate=1.0, seed=0)
@@ -53,15 +69,33 @@ def main():
                 shape = [1] * ref.ndim
                 shape[d] = p.n[d]
                 keep &= ~near.reshape(shape)
+        spread = {}
+        nrng = np.random.default_rng(7100 + k)
+
+        def rounded(v):
+            return v.astype(np.float32).astype(np.float64)
+
+        def noisy(v):
+            return rounded(v * (1.0 + 2.0 ** -23 * nrng.standard_normal(v.shape)))
+
+        old = oracle.set_dissipation(p.diss)
+        try:
+            for name, fn in (("storage", rounded), ("noise", noisy)):
+                got = _stepped(p, alpha, dt, fn)
+                spread[name] = float(np.abs(got - ref)[keep].max())
+        finally:
+            oracle.set_dissipation(old)
         band = np.flatnonzero(keep)
         rng = np.random.default_rng(5000 + k)
         band = rng.choice(band, size=min(512, band.size), replace=False)
         anywhere = rng.choice(ref.size, size=min(256, ref.size), replace=False)
-        lines.append("# request %d %s n %s steps %d band %d\n"
-                     % (k, p.dynamics, "x".join(map(str, p.n)), steps, band.size))
+        lines.append("# request %d %s n %s steps %d band %d storage_spread %.6e "
+                     "noise_spread %.6e\n"
+                     % (k, p.dynamics, "x".join(map(str, p.n)), steps, band.size,
+                        spread["storage"], spread["noise"]))
         lines.extend("%d %d 1 %.17g\n" % (k, i, ref.ravel()[i]) for i in np.sort(band))
         lines.extend("%d %d 0 %.17g\n" % (k, i, ref.ravel()[i]) for i in np.sort(anywhere))
-        print(k, p.dynamics, p.n, steps, flush=True)
+        print(k, p.dynamics, p.n, steps, spread, flush=True)
     path = os.path.join(HERE, "serving_stream_samples.txt")
     with open(path, "w") as f:
         f.write("# FP64 oracle, smallest request of each family of the 96-request serving "

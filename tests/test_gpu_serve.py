@@ -145,3 +145,42 @@ def test_served_solo_requests_equal_alone(solo_points):
     assert rep.completed == len(reqs)
     for j in jobs:
         assert np.array_equal(j.result, gpu_solve(j.problem, "fp32")), (j.rid, j.problem.n)
+
+
+def test_served_stream_requests_vs_oracle():
+    """The smallest request of each family of the 96-request benchmark stream,
+    served with FP64 results, against the FP64 oracle's stored values: the
+    front band within 1e-4 or, where larger, twice the oracle's own spread
+    under FP32-sized rounding of its state (both stored by
+    tests/golden/make_serving_samples.py)."""
+    import json
+    import os
+
+    from paper_2507_11542_amd.serve import GpuBackend, Server
+
+    gold = os.path.join(os.path.dirname(__file__), "golden", "serving_stream_samples.txt")
+    rows = np.loadtxt(gold)
+    spread = {}
+    with open(gold) as f:
+        for line in f:
+            w = line.split()
+            if line.startswith("# request"):
+                spread[int(w[2])] = float(w[w.index("noise_spread") + 1])
+    base = inputs.serving_stream(count=96, rate=1.0, seed=0)
+    ids = sorted(spread)
+    reqs = [inputs.Request(0.0, base[k].problem) for k in ids]
+    be = GpuBackend(prec="fp32", device_v0=True, fp64_finish=True)
+    try:
+        rep, jobs = Server(be, hbm_budget=8 << 30, macro_steps=16).run(reqs, keep_results=True)
+    finally:
+        be.close()
+    assert rep.completed == len(reqs)
+    for k, j in zip(ids, jobs):
+        sel = rows[rows[:, 0] == k]
+        err = np.abs(j.result.ravel()[sel[:, 1].astype(np.int64)] - sel[:, 3])
+        band = sel[:, 2] == 1
+        bar = max(1e-4, 2.0 * spread[k])
+        print(json.dumps({"request": k, "family": j.problem.dynamics,
+                          "band_err": float(err[band].max()), "bar": bar}), flush=True)
+        assert band.sum() > 100
+        assert err[band].max() <= bar
