@@ -253,7 +253,7 @@ hj_status hj_batch_create(hj_batch_t *out);
  * it has at least 512 of them when it can).  tile_nodes is checked in both
  * cases.  use_graph != 0 (default) replays a captured hipGraph instead of
  * launching directly: the handle keeps up to 16 graphs, each captured for one
- * kernel variant, launch shape and round count (flat launches: with each
+ * kernel variant, RK order, launch shape and round count (flat launches: with each
  * round's workgroup count rounded up to one of 8 sizes per power of two) and
  * replayed by any batch that fits it, and captures a new one when none does.
  * HJ_E_ARG out of range. */
