@@ -229,6 +229,15 @@ hj_status hj_rhs(hj_grid_t g, const void *V, void *L_out, void *hip_stream);
 hj_status hj_get_schedule(hj_grid_t g, double t0, double tf, double *alpha, double *dt,
                           int64_t *n_steps, void *hip_stream);
 
+/* Sec. 4 dissipation and CFL bound, and the length of the last solve:
+ * alpha (ndim doubles) of the current dynamics (reduced on the GPU on the
+ * null stream, with a synchronisation, if the handle has none cached), the
+ * CFL step dt, and the number of RK steps of the handle's last hj_solve or
+ * hj_solve_outputs (0 before the first; the steps of hj_solve_mixed count,
+ * hj_step does not).  Any output may be NULL.  HJ_E_STATE before
+ * hj_set_dynamics. */
+hj_status hj_get_info(hj_grid_t g, double *alpha, double *dt, int64_t *n_steps);
+
 /* ------------------------------------------------------------------------
  * Batched solves.  n independent grids that share ndim, dynamics kind,
  * derivative scheme (ENO2, ENO3 or WENO5), RK order (2 or 3), precision and device

@@ -93,6 +93,8 @@ def _load():
     lib.orc_set_dissipation.restype = I
     lib.orc_set_threads.argtypes = [I]
     lib.orc_set_threads.restype = I
+    lib.orc_set_storage_model.argtypes = [I]
+    lib.orc_set_storage_model.restype = I
     _lib = lib
     return lib
 
@@ -140,6 +142,20 @@ def set_dissipation(kind: str = "lf") -> str:
     over the grid-wide box; returns the previous kind."""
     old = int(_load().orc_set_dissipation(DISSIPATION[kind]))
     return {v: k for k, v in DISSIPATION.items()}[old]
+
+
+STORAGE_MODEL = {"fp64": 0, "stages": 1, "inputs": 2, "stages+inputs": 3}
+
+
+def set_storage_model(kind: str = "fp64") -> str:
+    """FP32 storage model of ``steps`` (a measurement aid, not the method):
+    "stages" rounds every RK stage result (so the state) to single precision
+    as it is stored, "inputs" rounds the tables, parameters, cell sizes, alpha
+    and the step size to single precision, "stages+inputs" both; the
+    arithmetic stays FP64.  "fp64" (the default) is the plain oracle.  Returns
+    the previous setting."""
+    old = int(_load().orc_set_storage_model(STORAGE_MODEL[kind]))
+    return {v: k for k, v in STORAGE_MODEL.items()}[old]
 
 
 def set_threads(n: int = 0) -> int:

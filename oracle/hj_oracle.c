@@ -104,6 +104,23 @@ enum { ORC_LF = 0, ORC_LLF = 1, ORC_GLF = 2 };
  * orc_set_dissipation before a call */
 static int g_diss = ORC_LF;
 
+/* FP32 storage model of orc_steps (a measurement aid for the single-precision
+ * form of the method, not part of the method; 0 = plain FP64, the default).
+ * ORC_ROUND_STAGES rounds every stage result of an RK step, and so the state,
+ * to the nearest single-precision value as it is stored.
+ * ORC_ROUND_INPUTS rounds what a single-precision evaluation holds in single
+ * precision: the node coordinates and their cos/sin, the dynamics parameters,
+ * the cell sizes and their reciprocals, alpha as the Lax-Friedrichs
+ * coefficient, and the step size.  The arithmetic itself stays FP64. */
+enum { ORC_ROUND_STAGES = 1, ORC_ROUND_INPUTS = 2 };
+static int g_store = 0;
+
+/* nearest single-precision value (round to nearest even) */
+static double round32(double x)
+{
+    return (double)(float)x;
+}
+
 typedef struct {
     int nd;
     long n[ORC_MAXD];
@@ -673,11 +690,37 @@ static void rhs_all(const ogrid *g, const odyn *dy, int scheme,
     }
 }
 
+/* the FP32 storage model: a stage result as it is stored */
+static void store_stage(const ogrid *g, double *w, int store)
+{
+    if (!(store & ORC_ROUND_STAGES)) return;
+    for (long k = 0; k < g->total; ++k) w[k] = round32(w[k]);
+}
+
+/* the FP32 storage model: the grid's tables and the dynamics parameters as
+ * a single-precision evaluation holds them */
+static void round_inputs(ogrid *g, odyn *dy)
+{
+    for (int d = 0; d < g->nd; ++d) {
+        g->dx[d] = round32(g->dx[d]);
+        g->inv_dx[d] = round32(g->inv_dx[d]);
+        g->inv_2dx[d] = round32(g->inv_2dx[d]);
+        g->inv_3dx[d] = round32(g->inv_3dx[d]);
+        for (long k = 0; k < g->n[d]; ++k) {
+            g->x[d][k] = round32(g->x[d][k]);
+            g->cs[d][k] = round32(g->cs[d][k]);
+            g->sn[d][k] = round32(g->sn[d][k]);
+        }
+    }
+    for (int k = 0; k < 8; ++k) dy->prm[k] = round32(dy->prm[k]);
+}
+
 /* Sec. 5 (odeCFL listing) and readings R7, R8, R11: one TVD-RK step of size h
- * applied in place to v.  w1, w2, l are scratch arrays of the grid size. */
+ * applied in place to v.  w1, w2, l are scratch arrays of the grid size.
+ * store: the FP32 storage model's flags (0 in every solve entry point). */
 static void rk_step(const ogrid *g, const odyn *dy, int scheme, int order,
                     const double *alpha, double h, double *v, const double *v0,
-                    int mode, double *w1, double *w2, double *l)
+                    int mode, double *w1, double *w2, double *l, int store)
 {
     long n = g->total;
     if (order == 1) {
@@ -686,6 +729,7 @@ static void rk_step(const ogrid *g, const odyn *dy, int scheme, int order,
     } else if (order == 2) {
         rhs_all(g, dy, scheme, alpha, v, l, mode);
         for (long k = 0; k < n; ++k) w1[k] = v[k] + h * l[k];
+        store_stage(g, w1, store);
         rhs_all(g, dy, scheme, alpha, w1, l, mode);
         for (long k = 0; k < n; ++k) {
             double v2 = w1[k] + h * l[k];
@@ -694,17 +738,20 @@ static void rk_step(const ogrid *g, const odyn *dy, int scheme, int order,
     } else {
         rhs_all(g, dy, scheme, alpha, v, l, mode);
         for (long k = 0; k < n; ++k) w1[k] = v[k] + h * l[k];
+        store_stage(g, w1, store);
         rhs_all(g, dy, scheme, alpha, w1, l, mode);
         for (long k = 0; k < n; ++k) {
             double v2 = w1[k] + h * l[k];
             w2[k] = (3.0 * v[k] + v2) / 4.0;
         }
+        store_stage(g, w2, store);
         rhs_all(g, dy, scheme, alpha, w2, l, mode);
         for (long k = 0; k < n; ++k) {
             double v3 = w2[k] + h * l[k];
             v[k] = (v[k] + 2.0 * v3) / 3.0;
         }
     }
+    store_stage(g, v, store);
     if (mode == ORC_TUBE)
         for (long k = 0; k < n; ++k)
             if (v0[k] < v[k]) v[k] = v0[k];
@@ -795,7 +842,9 @@ int orc_rhs_at(int nd, const long *n, const double *lo, const double *hi,
 }
 
 /* Advance v in place by `nsteps` TVD-RK steps of size h each (h is used as
- * given), with the tube update when mode is ORC_TUBE. alpha is supplied. */
+ * given), with the tube update when mode is ORC_TUBE. alpha is supplied.
+ * The FP32 storage model (orc_set_storage_model) applies to this entry point
+ * only. */
 int orc_steps(int nd, const long *n, const double *lo, const double *hi,
               unsigned pmask, int dyn, const double *prm, int nprm,
               int scheme, int order, const double *alpha, double h, long nsteps,
@@ -808,6 +857,13 @@ int orc_steps(int nd, const long *n, const double *lo, const double *hi,
         grid_free(&g);
         return -1;
     }
+    double a[ORC_MAXD] = {0, 0, 0, 0};
+    for (int d = 0; d < nd; ++d) a[d] = alpha[d];
+    if (g_store & ORC_ROUND_INPUTS) {
+        round_inputs(&g, &dy);
+        for (int d = 0; d < nd; ++d) a[d] = round32(a[d]);
+        h = round32(h);
+    }
     size_t bytes = sizeof(double) * (size_t)g.total;
     double *w1 = (double *)malloc(bytes), *w2 = (double *)malloc(bytes),
            *l = (double *)malloc(bytes);
@@ -816,7 +872,7 @@ int orc_steps(int nd, const long *n, const double *lo, const double *hi,
         rc = -2;
     } else {
         for (long s = 0; s < nsteps; ++s)
-            rk_step(&g, &dy, scheme, order, alpha, h, v, v0, mode, w1, w2, l);
+            rk_step(&g, &dy, scheme, order, a, h, v, v0, mode, w1, w2, l, g_store);
     }
     free(w1);
     free(w2);
@@ -863,7 +919,7 @@ long orc_solve(int nd, const long *n, const double *lo, const double *hi,
     if (tf > t0) {
         while (tf - t >= eps * (tf - t0)) {
             double h = dt < tf - t ? dt : tf - t;
-            rk_step(&g, &dy, scheme, order, alpha, h, v_out, v0, mode, w1, w2, l);
+            rk_step(&g, &dy, scheme, order, alpha, h, v_out, v0, mode, w1, w2, l, 0);
             t = t + h;
             ++steps;
         }
@@ -921,7 +977,7 @@ long orc_solve_outputs(int nd, const long *n, const double *lo, const double *hi
         if (tb > ta) {
             while (tb - t >= eps * (tb - ta)) {
                 double h = dt < tb - t ? dt : tb - t;
-                rk_step(&g, &dy, scheme, order, alpha, h, v, v0, step_mode, w1, w2, l);
+                rk_step(&g, &dy, scheme, order, alpha, h, v, v0, step_mode, w1, w2, l, 0);
                 t = t + h;
                 ++steps;
             }
@@ -1041,6 +1097,15 @@ int orc_set_dissipation(int kind)
 {
     int old = g_diss;
     g_diss = kind;
+    return old;
+}
+
+/* FP32 storage model of orc_steps (ORC_ROUND_STAGES | ORC_ROUND_INPUTS, or
+ * 0 for plain FP64); returns the previous setting */
+int orc_set_storage_model(int flags)
+{
+    int old = g_store;
+    g_store = flags;
     return old;
 }
 

@@ -475,6 +475,21 @@ hj_status hj_get_schedule(hj_grid_t g, double t0, double tf, double *alpha, doub
     return HJ_OK;
 }
 
+hj_status hj_get_info(hj_grid_t g, double *alpha, double *dt, int64_t *n_steps)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (!g->alpha_valid) {
+        if ((s = use_device(g)) != HJ_OK) return s;
+        if ((s = compute_alpha(g, nullptr)) != HJ_OK) return s;
+    }
+    if (alpha)
+        for (int k = 0; k < g->nd; ++k) alpha[k] = g->alpha[k];
+    if (dt) *dt = cfl_dt(g);
+    if (n_steps) *n_steps = g->last_steps;
+    return HJ_OK;
+}
+
 hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double tf, hj_mode mode,
                    void *hip_stream)
 {
@@ -491,6 +506,7 @@ hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double t
     if ((s = compute_alpha(g, st)) != HJ_OK) return s;
     std::vector<double> hs;
     schedule(cfl_dt(g), t0, tf, &hs);
+    g->last_steps = int64_t(hs.size());
     HJ_HIP(hipMemcpyAsync(V_out, V0, g->bytes(), hipMemcpyDeviceToDevice, st), "copy V0");
     if (g->prec == HJ_FP64) return run_steps<double>(g, V_out, V0, mode, hs, st);
     return run_steps<float>(g, V_out, V0, mode, hs, st);
@@ -563,11 +579,13 @@ hj_status hj_solve_outputs(hj_grid_t g, const void *V0, void *V_outs, double t0,
     const double dt = cfl_dt(g);
     double t = t0;
     const void *prev = V0;
+    g->last_steps = 0;
     for (int k = 0; k < ntimes; ++k) {
         void *out = (char *)V_outs + bytes * size_t(k);
         HJ_HIP(hipMemcpyAsync(out, prev, bytes, hipMemcpyDeviceToDevice, st), "copy V");
         std::vector<double> hs;
         schedule(dt, t, times[k], &hs);  // the interval's own loop
+        g->last_steps += int64_t(hs.size());
         if (g->prec == HJ_FP64)
             s = run_steps<double>(g, out, V0, mode, hs, st);
         else

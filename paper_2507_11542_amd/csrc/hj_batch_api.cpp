@@ -376,6 +376,11 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
             return fail(HJ_E_ARG, "V overlaps V0 for instance " + std::to_string(i));
         for (int j = 0; j < i; ++j) {
             const void *w0 = V0s ? V0s[j] : nullptr;
+            if (gs[j] == g)
+                return fail(HJ_E_ARG, "instances " + std::to_string(j) + " and " +
+                                          std::to_string(i) +
+                                          " use the same grid handle (its stage buffers "
+                                          "hold one instance)");
             if (overlap(Vs[i], g->bytes(), Vs[j], gs[j]->bytes()) ||
                 (w0 && overlap(Vs[i], g->bytes(), w0, gs[j]->bytes())))
                 return fail(HJ_E_ARG, "instances " + std::to_string(j) + " and " +
@@ -395,10 +400,38 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
         b->pending = false;
     }
 
+    // stage buffers: every instance's own, apart from every other instance's
+    // buffers and from every V and V0 of the batch (caller workspaces may be
+    // placed anywhere)
+    const bool need_b = g0->order == 3;
+    for (int i = 0; i < n; ++i)
+        if ((s = ensure_buffers(gs[i], need_b)) != HJ_OK) return s;
+    for (int i = 0; i < n; ++i) {
+        const size_t bi = gs[i]->bytes();
+        const void *own[2] = {gs[i]->bufA, need_b ? gs[i]->bufB : nullptr};
+        for (const void *w : own) {
+            if (!w) continue;
+            for (int j = 0; j < n; ++j) {
+                const size_t bj = gs[j]->bytes();
+                const void *v0 = V0s ? V0s[j] : nullptr;
+                bool clash = overlap(w, bi, Vs[j], bj) || (v0 && overlap(w, bi, v0, bj));
+                if (j != i) {
+                    clash = clash || overlap(w, bi, gs[j]->bufA, bj) ||
+                            (need_b && overlap(w, bi, gs[j]->bufB, bj));
+                }
+                if (clash)
+                    return fail(HJ_E_ARG, "stage buffers of instance " + std::to_string(i) +
+                                              " overlap arrays of instance " +
+                                              std::to_string(j));
+            }
+        }
+        if (need_b && overlap(gs[i]->bufA, bi, gs[i]->bufB, bi))
+            return fail(HJ_E_ARG, "stage buffers of instance " + std::to_string(i) + " overlap");
+    }
+
     // alpha for every instance that needs it (GPU reductions), one wait
     bool any = false;
     for (int i = 0; i < n; ++i) {
-        if ((s = ensure_buffers(gs[i], gs[i]->order == 3)) != HJ_OK) return s;
         if (fresh_alpha || !gs[i]->alpha_valid) {
             if ((s = launch_alpha_readback(gs[i], st)) != HJ_OK) return s;
             gs[i]->alpha_valid = false;

@@ -46,6 +46,7 @@ struct hj_grid_s {
     double *alpha_host = nullptr;  // pinned
     bool alpha_valid = false;
     double alpha[hj::kMaxDim] = {0, 0, 0, 0};
+    int64_t last_steps = 0;    // RK steps of the last hj_solve / hj_solve_outputs
 
     size_t elem() const { return prec == HJ_FP64 ? sizeof(double) : sizeof(float); }
     size_t bytes() const { return size_t(total) * elem(); }

@@ -11,6 +11,7 @@
 // on bounded axes, so no padded copy of the grid exists.
 #pragma once
 
+#include "hj_divseq.h"
 #include "hj_internal.h"
 
 namespace hj {
@@ -83,34 +84,16 @@ struct WenoR {
     T ra, rb, rc;
 };
 
-// FP64 division for the WENO weights: the fused-multiply-add divide sequence
-// (reciprocal estimate, two Newton steps, one residual correction) without
-// the range scaling and special-value fixup of the general divide.  Step for
-// step it is the general sequence in the case where that sequence does not
-// rescale, so it returns the correctly rounded quotient there: a nonzero
-// numerator and the denominator and quotient normal with exponents at least
-// 2^-970 and at most 2^1000 apart from overflow, or a zero numerator.  The
-// WENO denominators are (S + eps)^2 >= 1e-198 and sums of such weights, the
-// numerators 1 or weighted candidate sums, which stays inside that range for
-// any difference quotient of magnitude below 1e70.
-__device__ inline double div_rn_inrange(double a, double b)
-{
-    const double nb = -b;
-    const double r = __builtin_amdgcn_rcp(b);
-    const double y1 = fma(r, fma(nb, r, 1.0), r);
-    const double y2 = fma(y1, fma(nb, y1, 1.0), y1);
-    const double q = a * y2;
-    return fma(fma(nb, q, a), y2, q);
-}
+// FP64 division for the WENO weights: Newton-Raphson refinement of the
+// hardware reciprocal with Markstein's final correction (hj_divseq.h), the
+// correctly rounded quotient for every operand the weights can produce.
+struct HwRcp {
+    __device__ double operator()(double b) const { return __builtin_amdgcn_rcp(b); }
+};
 
-__device__ inline double rcp_rn_inrange(double b)
-{
-    const double nb = -b;
-    const double r = __builtin_amdgcn_rcp(b);
-    const double y1 = fma(r, fma(nb, r, 1.0), r);
-    const double y2 = fma(y1, fma(nb, y1, 1.0), y1);
-    return fma(fma(nb, y2, 1.0), y2, y2);
-}
+__device__ inline double div_rn_inrange(double a, double b) { return div_rn_seq(a, b, HwRcp()); }
+
+__device__ inline double rcp_rn_inrange(double b) { return rcp_rn_seq(b, HwRcp()); }
 
 template <typename T>
 __device__ inline T wrecip(T x)

@@ -93,6 +93,7 @@ def _load():
     lib.hj_init_shapes.argtypes = [P, P, P, I, P]
     lib.hj_rhs.argtypes = [P, P, P, P]
     lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
+    lib.hj_get_info.argtypes = [P, PD, PD, PI64]
     lib.hj_grid_destroy.argtypes = [P]
     lib.hj_grid_set_workspace.argtypes = [P, P, P]
     lib.hj_batch_create.argtypes = [ctypes.POINTER(P)]
@@ -106,7 +107,7 @@ def _load():
     lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
                  "hj_solve_mixed", "hj_tube_finish", "hj_solve_outputs", "hj_init_shapes",
-                 "hj_set_dissipation", "hj_rhs", "hj_get_schedule", "hj_grid_destroy", "hj_grid_set_workspace",
+                 "hj_set_dissipation", "hj_rhs", "hj_get_schedule", "hj_get_info", "hj_grid_destroy", "hj_grid_set_workspace",
                  "hj_batch_create",
                  "hj_batch_config", "hj_solve_batch", "hj_step_batch", "hj_batch_wait",
                  "hj_batch_destroy"):
@@ -144,6 +145,24 @@ def _ptr(x) -> Optional[int]:
     if isinstance(x, int):
         return x
     return x.data_ptr()
+
+
+def _check_array(x, dtype_name: str, numel: int, what: str):
+    """A tensor passed as a device array must be a contiguous GPU tensor of
+    the element type and node count the call expects (raw integer pointers
+    are the caller's responsibility).  Raises ValueError before any library
+    call, so a wrong tensor never reaches a kernel."""
+    if x is None or isinstance(x, int):
+        return
+    dt = str(getattr(x, "dtype", ""))
+    if not dt.endswith(dtype_name):
+        raise ValueError("%s: dtype %s, expected %s" % (what, dt or type(x).__name__, dtype_name))
+    if x.numel() != numel:
+        raise ValueError("%s: %d elements, expected %d" % (what, x.numel(), numel))
+    if not x.is_contiguous():
+        raise ValueError("%s: not contiguous" % what)
+    if not x.is_cuda:
+        raise ValueError("%s: not a GPU tensor" % what)
 
 
 def _stream(s) -> Optional[int]:
@@ -231,6 +250,15 @@ def hj_get_schedule(g, t0: float, tf: float, ndim: int, stream=None):
     return [alpha[k] for k in range(ndim)], dt.value, steps.value
 
 
+def hj_get_info(g, ndim: int):
+    """(alpha, dt, steps of the last solve) of a grid handle."""
+    alpha = (ctypes.c_double * 4)()
+    dt = ctypes.c_double(0.0)
+    steps = ctypes.c_int64(0)
+    _check(_lib.hj_get_info(g, alpha, ctypes.byref(dt), ctypes.byref(steps)))
+    return [alpha[k] for k in range(ndim)], dt.value, steps.value
+
+
 def hj_grid_destroy(g):
     _check(_lib.hj_grid_destroy(g))
 
@@ -304,11 +332,23 @@ class Batch:
         self.tile_nodes, self.workgroups, self.use_graph = tile_nodes, workgroups, use_graph
         hj_batch_config(self.handle, tile_nodes, workgroups, use_graph)
 
+    @staticmethod
+    def _check(grids, *arrays):
+        for arr, what in arrays:
+            if arr is None:
+                continue
+            if len(arr) != len(grids):
+                raise ValueError("%s: %d arrays for %d grids" % (what, len(arr), len(grids)))
+            for i, (g, x) in enumerate(zip(grids, arr)):
+                g._check(x, "%s[%d]" % (what, i))
+
     def solve(self, grids, V0s, Vouts, t0s, tfs, modes, stream=None):
+        self._check(grids, (V0s, "V0s"), (Vouts, "Vouts"))
         hj_solve_batch(self.handle, [g.handle for g in grids], V0s, Vouts, t0s, tfs,
                        [MODE[m] if isinstance(m, str) else m for m in modes], stream)
 
     def step(self, grids, V0s, Vs, t0s, ts, tfs, modes, max_steps, stream=None):
+        self._check(grids, (V0s, "V0s"), (Vs, "Vs"))
         return hj_step_batch(self.handle, [g.handle for g in grids], V0s, Vs, t0s, ts, tfs,
                              [MODE[m] if isinstance(m, str) else m for m in modes], max_steps,
                              stream)
@@ -346,6 +386,17 @@ class Grid:
         g.set_dissipation(getattr(p, "diss", "lf"))
         return g
 
+    @property
+    def points(self) -> int:
+        n = 1
+        for v in self.n:
+            n *= v
+        return n
+
+    def _check(self, x, what, dtype=None, count=1):
+        _check_array(x, dtype or ("float64" if self.prec == "fp64" else "float32"),
+                     count * self.points, what)
+
     def set_dynamics(self, name: str, params):
         hj_set_dynamics(self.handle, DYN[name], params)
 
@@ -356,35 +407,55 @@ class Grid:
         hj_set_dissipation(self.handle, DISSIPATION[kind])
 
     def solve(self, V0, V_out, t0, tf, mode="set", stream=None):
+        self._check(V0, "V0")
+        self._check(V_out, "V_out")
         hj_solve(self.handle, V0, V_out, t0, tf, MODE[mode], stream)
 
     def init_shapes(self, V_out, shape_list, stream=None):
         """V_out <- the implicit surface of shape_list (dicts as in make_shapes)."""
+        self._check(V_out, "V_out")
         hj_init_shapes(self.handle, V_out, shape_list, stream)
 
     def solve_outputs(self, V0, V_outs, t0, times, mode="set", stream=None):
         """V_outs: device array of len(times) * prod(n) elements (for example a
         tensor of shape (len(times),) + n)."""
+        self._check(V0, "V0")
+        self._check(V_outs, "V_outs", count=len(times))
         hj_solve_outputs(self.handle, V0, V_outs, t0, times, MODE[mode], stream)
 
     def step(self, V, V0, t, tf, mode="set", stream=None):
+        self._check(V, "V")
+        self._check(V0, "V0")
         return hj_step(self.handle, V, V0, t, tf, MODE[mode], stream)
 
     def solve_mixed(self, V0, V_out, t0, tf, mode="set", band=-1.0, stream=None):
+        self._check(V0, "V0", "float64")
+        self._check(V_out, "V_out", "float64")
         hj_solve_mixed(self.handle, V0, V_out, t0, tf, MODE[mode], band, stream)
 
     def tube_finish(self, V32, V0, V_out, mode="set", band=-1.0, stream=None):
+        self._check(V32, "V32", "float32")
+        self._check(V0, "V0", "float64")
+        self._check(V_out, "V_out", "float64")
         hj_tube_finish(self.handle, V32, V0, V_out, MODE[mode], band, stream)
 
     def rhs(self, V, L_out, stream=None):
+        self._check(V, "V")
+        self._check(L_out, "L_out")
         hj_rhs(self.handle, V, L_out, stream)
 
     def set_workspace(self, A, B):
+        self._check(A, "A")
+        self._check(B, "B")
         hj_grid_set_workspace(self.handle, A, B)
         self._workspace = (A, B)  # keep the tensors alive with the grid
 
     def schedule(self, t0, tf, stream=None):
         return hj_get_schedule(self.handle, t0, tf, len(self.n), stream)
+
+    def info(self):
+        """(alpha, dt, RK steps of the last solve)."""
+        return hj_get_info(self.handle, len(self.n))
 
     def close(self):
         if self.handle is not None:

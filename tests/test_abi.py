@@ -20,7 +20,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
-                 "hj_solve_batch", "hj_grid_destroy", "hj_last_error"):
+                 "hj_solve_batch", "hj_get_info", "hj_grid_destroy", "hj_last_error"):
         assert must in names
 
 
@@ -62,6 +62,7 @@ def test_argument_errors_without_device():
                               None) == hj.HJ_E_ARG
     assert lib.hj_step(None, None, None, None, 1.0, 0, None, None) == hj.HJ_E_ARG
     assert lib.hj_rhs(None, None, None, None) == hj.HJ_E_ARG
+    assert lib.hj_get_info(None, None, None, None) == hj.HJ_E_ARG
     assert lib.hj_tube_finish(None, None, None, None, 1, -1.0, None) == hj.HJ_E_ARG
     assert lib.hj_solve_mixed(None, None, None, 0.0, 1.0, 1, -1.0, None) == hj.HJ_E_ARG
     assert lib.hj_batch_config(None, 4096, 1024, 1) == hj.HJ_E_ARG

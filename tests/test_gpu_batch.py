@@ -179,6 +179,51 @@ def test_batch_rejects_mixed_instances():
         b.close()
 
 
+def test_batch_rejects_shared_stage_buffers():
+    """Two instances on one grid handle, or on two handles whose stage
+    buffers overlap (caller workspaces), would write the same stage buffers
+    in one round: HJ_E_ARG, before any launch."""
+    import torch
+
+    from gpu_util import to_dev
+    from paper_2507_11542_amd import hj
+
+    p = inputs.rel_dubins_3d(n=(11, 11, 11), tf=0.1)
+    b = hj.Batch()
+    g, h = hj.Grid.from_problem(p), hj.Grid.from_problem(p)
+    v0a, v0b = to_dev(p.v0()), to_dev(p.v0() + 0.5)
+    outs = [torch.empty_like(v0a), torch.empty_like(v0a)]
+    try:
+        with pytest.raises(hj.HJError) as ei:
+            b.solve([g, g], [v0a, v0b], outs, [0, 0], [0.1, 0.1], ["tube", "tube"])
+        assert ei.value.status == hj.HJ_E_ARG and "same grid" in str(ei.value)
+        ws = torch.empty(3 * p.points, dtype=torch.float64, device="cuda")
+        g.set_workspace(ws[: p.points], ws[p.points: 2 * p.points])
+        h.set_workspace(ws[p.points: 2 * p.points], ws[2 * p.points:])
+        with pytest.raises(hj.HJError) as ei:
+            b.solve([g, h], [v0a, v0b], outs, [0, 0], [0.1, 0.1], ["tube", "tube"])
+        assert ei.value.status == hj.HJ_E_ARG and "stage buffers" in str(ei.value)
+        with pytest.raises(hj.HJError) as ei:  # a workspace that is an output
+            h.set_workspace(outs[0], ws[2 * p.points:])
+            b.solve([g, h], [v0a, v0b], outs, [0, 0], [0.1, 0.1], ["tube", "tube"])
+        assert ei.value.status == hj.HJ_E_ARG
+        # apart, the two handles solve and equal their plain solves
+        h.set_workspace(torch.empty(p.points, dtype=torch.float64, device="cuda"),
+                        torch.empty(p.points, dtype=torch.float64, device="cuda"))
+        b.solve([g, h], [v0a, v0b], outs, [0, 0], [0.1, 0.1], ["tube", "tube"])
+        b.wait(2)
+        torch.cuda.synchronize()
+        for v0, out in zip((v0a, v0b), outs):
+            ref = torch.empty_like(v0)
+            g.solve(v0, ref, 0.0, 0.1, "tube", torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            assert torch.equal(ref, out)
+    finally:
+        g.close()
+        h.close()
+        b.close()
+
+
 def _batch_golden():
     """Stored FP64-oracle front-band values of the batch's 51^3 instances and
     the oracle's own spread under FP32-sized rounding of its state, keyed by

@@ -80,6 +80,31 @@ def test_schedule_matches_oracle(orc, name, p):
     assert dt == rdt and k == rk
 
 
+def test_get_info_after_solve(orc):
+    """hj_get_info: alpha and dt of the oracle's schedule, and the step count
+    of the last hj_solve (0 before it); computing alpha itself when no solve
+    has cached it."""
+    import torch
+
+    from gpu_util import to_dev
+    from paper_2507_11542_amd import hj
+
+    p = inputs.rel_dubins_3d(n=(17, 15, 12), tf=0.3)
+    ra, rdt, rk, _ = orc.schedule(*p.grid_args(), p.dynamics, p.params, p.cfl, p.t0, p.tf)
+    g = hj.Grid.from_problem(p, "fp64")
+    try:
+        alpha, dt, steps = g.info()
+        assert list(alpha) == list(ra) and dt == rdt and steps == 0
+        d0 = to_dev(p.v0())
+        out = torch.empty_like(d0)
+        g.solve(d0, out, p.t0, p.tf, p.mode, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        alpha, dt, steps = g.info()
+        assert list(alpha) == list(ra) and dt == rdt and steps == rk
+    finally:
+        g.close()
+
+
 @pytest.mark.parametrize("scheme", ["upwind1", "eno2", "eno3", "weno5"])
 @pytest.mark.parametrize("dyn", ["rel_dubins", "dubins4d", "double_integrator"])
 def test_rhs_matches_oracle_on_rough_data(orc, scheme, dyn):
