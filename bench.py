@@ -69,16 +69,62 @@ def measured_traffic(prec: str):
     return 1024.0 * (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"])
 
 
-def weno5_flops_per_node_stage(ndim: int) -> float:
-    """Algorithmic floating-point operations of one stage at one node, counted
-    on the formulas (Sec. 3.3, 4, 5), not on the GPU instruction stream:
-    per axis 6 first differences (6 sub + 6 div) and two WENO5 evaluations of
-    78 operations each (candidates 15, smoothness 33, eps 11, weights 9,
-    normalisation and blend 10); then p-bar 2/axis, LF dissipation 4/axis,
-    the relative-Dubins Hamiltonian 17, the sign 1 and the RK blend (average
-    of the three RK3 stages) 13/3."""
-    per_axis = 12 + 2 * 78
+# Floating-point operations of the WENO5 formulas (Sec. 3.3), counted on the
+# formulas: a window of five first differences w0..w4 (smoothness of the three
+# substencils 33, eps = 1e-6 max w^2 + floor 7 with the four maxima, the three
+# reciprocal weights (S + eps)^-2 9) and one blend of the third-order
+# candidates with them (candidates 15, linear weights 3, weighted sum 5,
+# normalisation 3).
+WENO_WINDOW_FLOPS = 33 + 7 + 9
+WENO_BLEND_FLOPS = 15 + 3 + 5 + 3
+
+
+def weno5_flops_per_node_stage(ndim: int, executed: bool = False) -> float:
+    """Floating-point operations of one RK stage at one node of the WENO5 +
+    Lax-Friedrichs + RK3 relative-Dubins step (Sec. 3.3, 4, 5).
+
+    The method's count (executed=False): along each axis a node adds one first
+    difference (a subtraction and the 1/dx scaling) and one WENO window, the
+    one centred on the interface to its right, which serves the right-biased
+    derivative of the node and the left-biased one of its neighbour; two blends
+    give p- and p+.  Then p-bar 2/axis, the Lax-Friedrichs term 4/axis, the
+    Hamiltonian 17, the sign 1 and the RK combination (13/3, the average of
+    the three stages).
+
+    The executed count (executed=True) is what the per-node kernel evaluates:
+    every node forms its six first differences per axis and both of its
+    windows itself."""
+    if executed:
+        per_axis = 6 * 2 + 2 * WENO_WINDOW_FLOPS + 2 * WENO_BLEND_FLOPS
+    else:
+        per_axis = 2 + WENO_WINDOW_FLOPS + 2 * WENO_BLEND_FLOPS
     return ndim * (per_axis + 2 + 4) + 17 + 1 + 13.0 / 3.0
+
+
+def stage_launch_time(g, v0, out, p, stream, reps: int = 3):
+    """Average duration of one stage launch of the solve: HIP events on the
+    launch stream around whole hj_solve calls over [t0, tf] and [t0, tf/2]
+    (best of `reps` each).  Their difference is K1 - K2 RK steps of three
+    back-to-back launches, free of what both calls share (the alpha
+    reduction, its read-back, the V0 copy), so launches x this time stays
+    within the solve's wall time.  Also returns the per-launch time of the
+    whole [t0, tf] solve (those shared parts included)."""
+    import torch
+
+    res = {}
+    for tf in (p.tf, 0.5 * (p.t0 + p.tf)):
+        best = float("inf")
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g.solve(v0, out, p.t0, tf, p.mode, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3)
+        res[tf] = (best, g.schedule(p.t0, tf, stream)[2])
+    (t1, k1), (t2, k2) = res[p.tf], res[0.5 * (p.t0 + p.tf)]
+    return (t1 - t2) / (3 * (k1 - k2)), t1 / (3 * k1)
 
 
 def bytes_per_node_stage(elem: int, tube: bool) -> float:
@@ -346,20 +392,26 @@ def bench_served(args):
         return rep.as_dict()
 
     def accuracy():
-        """The smallest request of each family served again (all at once;
-        results do not depend on the mix) against the FP64 oracle's stored
-        values."""
+        """The smallest and the largest request of each family served again
+        (all at once; a result does not depend on the mix) against the FP64
+        oracle's stored values, beside the storage spread: how far the FP64
+        method itself moves with single-precision storage."""
         gold = os.path.join(ROOT, "tests", "golden", "serving_stream_samples.txt")
-        if not os.path.exists(gold) or n != 96:
+        if not os.path.exists(gold) or n != 256:
             return None
         rows = np.loadtxt(gold)
         spread = {}
         with open(gold) as f:
             for line in f:
                 w = line.split()
-                if line.startswith("# request") and "noise_spread" in w:
-                    spread[int(w[2])] = (float(w[w.index("storage_spread") + 1]),
-                                         float(w[w.index("noise_spread") + 1]))
+                if line.startswith("# request"):
+                    vals = []
+                    for x in w[w.index("storage_spread") + 1:]:
+                        try:
+                            vals.append(float(x))
+                        except ValueError:
+                            break
+                    spread[int(w[2])] = max(vals) if vals else None
         ids = sorted({int(k) for k in rows[:, 0]})
         reqs = [inputs.Request(0.0, base[k].problem) for k in ids]
         be = GpuBackend(prec="fp32", v0_cache={i: v0_cache[k] for i, k in enumerate(ids)}
@@ -371,17 +423,17 @@ def bench_served(args):
                              macro_updates=args.macro_updates).run(reqs, keep_results=True)
         finally:
             be.close()
-        out = {}
+        out = []
         for k, j in zip(ids, jobs):
             sel = rows[rows[:, 0] == k]
             err = np.abs(j.result.ravel()[sel[:, 1].astype(np.int64)] - sel[:, 3])
             band = sel[:, 2] == 1
-            out[j.problem.dynamics] = {
-                "request": k, "grid": list(j.problem.n), "horizon": j.problem.tf,
+            out.append({
+                "request": k, "dynamics": j.problem.dynamics, "grid": list(j.problem.n),
+                "horizon": j.problem.tf,
                 "band_max_abs": float(err[band].max()) if band.any() else None,
                 "sampled_max_abs": float(err.max()),
-                "oracle_storage_spread": spread.get(k, (None, None))[0],
-                "oracle_noise_spread": spread.get(k, (None, None))[1]}
+                "oracle_storage_spread": spread.get(k)})
         return out
 
     sat = served(1e9)  # everything arrives at once: saturated throughput
@@ -398,7 +450,15 @@ def bench_served(args):
                    if args.device_v0 else "uploaded from the host per request"),
             "results": ("FP64: FP32 solve, tube minimum retaken in FP64 on |V| <= 3 max dx"
                         if args.fp64_finish else "FP32"),
-            "saturated_rate_req_per_s": lam_sat, "served": runs, "plain": plains,
+            "saturated_rate_req_per_s": lam_sat,
+            "by_rate": {k: {"served_updates_per_s": runs[k]["updates_per_s"],
+                            "plain_updates_per_s": plains[k]["updates_per_s"],
+                            "served_vs_plain": runs[k]["updates_per_s"]
+                            / plains[k]["updates_per_s"],
+                            "served_p50_s": runs[k]["p50_s"], "served_p99_s": runs[k]["p99_s"],
+                            "plain_p50_s": plains[k]["p50_s"], "plain_p99_s": plains[k]["p99_s"]}
+                        for k in runs},
+            "served": runs, "plain": plains,
             "served_vs_oracle_fp64": accuracy(),
             "served_vs_plain_updates_per_s":
                 sat["updates_per_s"] / plains["saturated"]["updates_per_s"]}
@@ -411,16 +471,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-steps", type=int, default=40,
-                    help="RK steps timed with HIP events for the kernel roofline")
     ap.add_argument("--no-rockets", action="store_true",
                     help="skip the rockets and 4-D Dubins legs")
     ap.add_argument("--rockets-reps", type=int, default=5)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=96)
-    ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.5, 0.9])
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[0.5, 0.9, 1.2])
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--host-v0", dest="device_v0", action="store_false",
                     help="serving legs upload V0 from the host instead of building it on "
@@ -468,19 +526,9 @@ def main() -> int:
     ms_per_step = 1e3 * elapsed / args.steps
     value = updates_per_solve * args.steps / elapsed
 
-    # dominant kernel: the fused stage kernel, 3 launches per RK3 step
-    vk = v0.clone()
-    tt = 0.0
-    for _ in range(3):
-        tt, _ = g.step(vk, v0, tt, p.tf, p.mode, stream)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_steps):
-        tt, _ = g.step(vk, v0, tt, p.tf, p.mode, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    launch_s = e0.elapsed_time(e1) / 1e3 / (3 * args.kernel_steps)
+    # dominant kernel: the fused stage kernel, 3 launches per RK3 step, timed
+    # on the stream it is launched on by the differential of two solves
+    launch_s, step_launch_s = stage_launch_time(g, v0, torch.empty_like(out), p, stream)
     flops = weno5_flops_per_node_stage(p.ndim) * p.points
     achieved = flops / launch_s / 1e12
     peak = FP64_PEAK_TFLOPS if args.prec == "fp64" else FP32_PEAK_TFLOPS
@@ -525,11 +573,16 @@ def main() -> int:
                      "traffic_unit": "bytes per launch",
                      "kernel": "stage_kernel<%s,3,WENO5,REL_DUBINS>" % args.prec,
                      "launch_us": launch_s * 1e6,
+                     "launch_us_whole_solve": step_launch_s * 1e6,
+                     "launches_per_solve": 3 * nsteps,
                      "algorithmic_hbm_GBs": hbm_gbs,
                      "measured_hbm_GBs": (measured_traffic(args.prec) / launch_s / 1e9
                                           if measured_traffic(args.prec) else None),
                      "hbm_peak_GBs": 8000.0,
-                     "flops_per_node_stage": weno5_flops_per_node_stage(p.ndim)},
+                     "flops_per_node_stage": weno5_flops_per_node_stage(p.ndim),
+                     "flops_per_node_stage_executed":
+                         weno5_flops_per_node_stage(p.ndim, executed=True),
+                     "flop_count": "the method's: one WENO window per interface per axis"},
         "error_vs_oracle_fp64": err,
     }
     if not args.no_rockets:

@@ -306,6 +306,16 @@ hj_status hj_batch_wait(hj_batch_t b, void *hip_stream, double *t_final, int64_t
 /* Frees the engine (waits for its last batch).  NULL is accepted. */
 hj_status hj_batch_destroy(hj_batch_t b);
 
+/* Optional check of solve results: with HJ_CHECK_FINITE set, hj_solve,
+ * hj_solve_outputs and hj_solve_mixed scan their result on
+ * the device for NaN or infinite values after the last stage, wait for the
+ * stream, and return HJ_E_NUMERIC if any is found (the result is written
+ * either way).  Off by default: a solve then returns after enqueueing.
+ * hj_step and batches are not checked.  Enabling it allocates a device flag.
+ * HJ_E_ARG on unknown flags. */
+enum { HJ_CHECK_FINITE = 1 };
+hj_status hj_set_check(hj_grid_t g, int flags);
+
 /* Caller-owned stage buffers: A and B are device arrays of prod(N) elements
  * of the grid's element type, not overlapping each other or any V passed to
  * this grid's solves; the handle uses them instead of allocating its own

@@ -323,9 +323,88 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 
 }  // namespace
 
+namespace hj {
+
+hj_status solve_check(hj_grid_t g, const void *V0, const void *V_out, double t0, double tf,
+                      hj_mode mode)
+{
+    hj_status s = check_ready(g);
+    if (s != HJ_OK) return s;
+    if (!V0 || !V_out) return fail(HJ_E_ARG, "V0 and V_out must be non-NULL");
+    if (!known_mode(mode)) return fail(HJ_E_ARG, "unknown mode");
+    if (!(std::isfinite(t0) && std::isfinite(tf) && tf >= t0))
+        return fail(HJ_E_ARG, "need finite t0 <= tf");
+    if (overlap(V0, V_out, g->bytes())) return fail(HJ_E_ARG, "V_out overlaps V0");
+    return HJ_OK;
+}
+
+// The body of hj_solve with the stage buffers A and B given (B unused below
+// RK3): alpha (one synchronisation), the schedule, V_out <- V0 and the step
+// launches, all on st.  The handle's own buffers are restored before return;
+// the launches already hold A and B by value.
+hj_status solve_enqueue(hj_grid_t g, const void *V0, void *V_out, double t0, double tf,
+                        hj_mode mode, void *A, void *B, hipStream_t st)
+{
+    hj_status s = compute_alpha(g, st);
+    if (s != HJ_OK) return s;
+    std::vector<double> hs;
+    schedule(cfl_dt(g), t0, tf, &hs);
+    g->last_steps = int64_t(hs.size());
+    HJ_HIP(hipMemcpyAsync(V_out, V0, g->bytes(), hipMemcpyDeviceToDevice, st), "copy V0");
+    void *own_a = g->bufA, *own_b = g->bufB;
+    g->bufA = A;
+    g->bufB = B;
+    if (g->prec == HJ_FP64)
+        s = run_steps<double>(g, V_out, V0, mode, hs, st);
+    else
+        s = run_steps<float>(g, V_out, V0, mode, hs, st);
+    g->bufA = own_a;
+    g->bufB = own_b;
+    return s;
+}
+
+hj_status check_result(hj_grid_t g, const void *V, size_t n, bool fp64, hipStream_t st)
+{
+    if (!(g->check & HJ_CHECK_FINITE)) return HJ_OK;
+    for (size_t off = 0; off < n; off += size_t(1) << 30) {
+        const size_t m = n - off < (size_t(1) << 30) ? n - off : (size_t(1) << 30);
+        const void *p = (const char *)V + off * (fp64 ? 8 : 4);
+        hipError_t e = launch_scan_nonfinite(p, fp64 ? 1 : 0, uint32_t(m), g->check_dev, st);
+        if (e != hipSuccess) return hip_fail(e, "non-finite scan");
+        HJ_HIP(hipMemcpyAsync(g->check_host, g->check_dev, sizeof(int), hipMemcpyDeviceToHost,
+                              st),
+               "non-finite scan read-back");
+        HJ_HIP(hipStreamSynchronize(st), "non-finite scan synchronise");
+        if (*g->check_host)
+            return fail(HJ_E_NUMERIC, "the result holds NaN or infinite values");
+    }
+    return HJ_OK;
+}
+
+}  // namespace hj
+
 extern "C" {
 
 const char *hj_last_error(void) { return g_err.c_str(); }
+
+hj_status hj_set_check(hj_grid_t g, int flags)
+{
+    if (!g) return fail(HJ_E_ARG, "null grid handle");
+    if (flags & ~HJ_CHECK_FINITE) return fail(HJ_E_ARG, "unknown check flags");
+    if (flags & HJ_CHECK_FINITE) {
+        hj_status s = use_device(g);
+        if (s != HJ_OK) return s;
+        if (!g->check_dev &&
+            (s = dev_alloc((void **)&g->check_dev, sizeof(int), "check flag")) != HJ_OK)
+            return s;
+        if (!g->check_host) {
+            hipError_t e = hipHostMalloc((void **)&g->check_host, sizeof(int), 0);
+            if (e != hipSuccess) return hip_fail(e, "pinned check flag");
+        }
+    }
+    g->check = flags;
+    return HJ_OK;
+}
 
 const char *hj_version(void) { return "libhj 0.1 (gfx950)"; }
 
@@ -493,23 +572,13 @@ hj_status hj_get_info(hj_grid_t g, double *alpha, double *dt, int64_t *n_steps)
 hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double tf, hj_mode mode,
                    void *hip_stream)
 {
-    hj_status s = check_ready(g);
+    hj_status s = solve_check(g, V0, V_out, t0, tf, mode);
     if (s != HJ_OK) return s;
-    if (!V0 || !V_out) return fail(HJ_E_ARG, "V0 and V_out must be non-NULL");
-    if (!known_mode(mode)) return fail(HJ_E_ARG, "unknown mode");
-    if (!(std::isfinite(t0) && std::isfinite(tf) && tf >= t0))
-        return fail(HJ_E_ARG, "need finite t0 <= tf");
-    if (overlap(V0, V_out, g->bytes())) return fail(HJ_E_ARG, "V_out overlaps V0");
-    hipStream_t st = (hipStream_t)hip_stream;
     if ((s = use_device(g)) != HJ_OK) return s;
     if ((s = ensure_buffers(g, g->order == 3)) != HJ_OK) return s;
-    if ((s = compute_alpha(g, st)) != HJ_OK) return s;
-    std::vector<double> hs;
-    schedule(cfl_dt(g), t0, tf, &hs);
-    g->last_steps = int64_t(hs.size());
-    HJ_HIP(hipMemcpyAsync(V_out, V0, g->bytes(), hipMemcpyDeviceToDevice, st), "copy V0");
-    if (g->prec == HJ_FP64) return run_steps<double>(g, V_out, V0, mode, hs, st);
-    return run_steps<float>(g, V_out, V0, mode, hs, st);
+    hipStream_t st = (hipStream_t)hip_stream;
+    if ((s = solve_enqueue(g, V0, V_out, t0, tf, mode, g->bufA, g->bufB, st)) != HJ_OK) return s;
+    return check_result(g, V_out, size_t(g->total), g->prec == HJ_FP64, st);
 }
 
 hj_status hj_init_shapes(hj_grid_t g, void *V_out, const hj_shape *shapes, int nshapes,
@@ -594,7 +663,7 @@ hj_status hj_solve_outputs(hj_grid_t g, const void *V0, void *V_outs, double t0,
         t = times[k];
         prev = out;
     }
-    return HJ_OK;
+    return check_result(g, V_outs, size_t(g->total) * size_t(ntimes), g->prec == HJ_FP64, st);
 }
 
 hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0, double tf,
@@ -616,8 +685,15 @@ hj_status hj_solve_mixed(hj_grid_t g, const double *V0, double *V_out, double t0
     if (!g->mixV0 && (s = dev_alloc(&g->mixV0, g->bytes(), "mixed V0")) != HJ_OK) return s;
     hipError_t e = launch_round_to_f32(V0, (float *)g->mixV0, uint32_t(g->total), st);
     if (e != hipSuccess) return hip_fail(e, "round to fp32");
-    if ((s = hj_solve(g, g->mixV0, g->mixV, t0, tf, mode, hip_stream)) != HJ_OK) return s;
-    return hj_tube_finish(g, (const float *)g->mixV, V0, V_out, mode, band, hip_stream);
+    const int check = g->check;
+    g->check = 0;  // the FP64 result is checked below, not the FP32 working array
+    s = hj_solve(g, g->mixV0, g->mixV, t0, tf, mode, hip_stream);
+    g->check = check;
+    if (s != HJ_OK) return s;
+    if ((s = hj_tube_finish(g, (const float *)g->mixV, V0, V_out, mode, band, hip_stream)) !=
+        HJ_OK)
+        return s;
+    return check_result(g, V_out, size_t(g->total), true, st);
 }
 
 hj_status hj_tube_finish(hj_grid_t g, const float *V32, const double *V0, double *V_out,
@@ -721,6 +797,8 @@ hj_status hj_grid_destroy(hj_grid_t g)
     if (g->partial) (void)hipFree(g->partial);
     if (g->alpha_dev) (void)hipFree(g->alpha_dev);
     if (g->alpha_host) (void)hipHostFree(g->alpha_host);
+    if (g->check_dev) (void)hipFree(g->check_dev);
+    if (g->check_host) (void)hipHostFree(g->check_host);
     delete g;
     return HJ_OK;
 }

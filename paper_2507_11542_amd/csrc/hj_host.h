@@ -47,6 +47,9 @@ struct hj_grid_s {
     bool alpha_valid = false;
     double alpha[hj::kMaxDim] = {0, 0, 0, 0};
     int64_t last_steps = 0;    // RK steps of the last hj_solve / hj_solve_outputs
+    int check = 0;             // HJ_CHECK_* flags (hj_set_check)
+    int *check_dev = nullptr;  // device flag of the non-finite scan
+    int *check_host = nullptr; // pinned read-back of it
 
     size_t elem() const { return prec == HJ_FP64 ? sizeof(double) : sizeof(float); }
     size_t bytes() const { return size_t(total) * elem(); }
@@ -70,6 +73,14 @@ void schedule(double dt, double t0, double tf, std::vector<double> *hs);
 extern const double kEpsT;
 template <typename T>
 StageArgs<T> base_args(hj_grid_t g);
+// hj_solve's argument checks, and its body with given stage buffers
+hj_status solve_check(hj_grid_t g, const void *V0, const void *V_out, double t0, double tf,
+                      hj_mode mode);
+// HJ_CHECK_FINITE: scan n values of V (grid precision, or FP64 when fp64) for
+// NaN/Inf after the work on st, wait for it, HJ_E_NUMERIC if any
+hj_status check_result(hj_grid_t g, const void *V, size_t n, bool fp64, hipStream_t st);
+hj_status solve_enqueue(hj_grid_t g, const void *V0, void *V_out, double t0, double tf,
+                        hj_mode mode, void *A, void *B, hipStream_t st);
 
 }  // namespace hj
 

@@ -119,6 +119,9 @@ struct ShapeArgs {
 };
 
 hipError_t launch_shapes(const ShapeArgs &a, hipStream_t s);
+// flag <- 1 if any of the n values (double if fp64, else float) is NaN or
+// infinite, else 0 (flag is one device int)
+hipError_t launch_scan_nonfinite(const void *v, int fp64, uint32_t n, int *flag, hipStream_t s);
 hipError_t launch_finalize_f64(const float *v32, const double *v0, double *out, uint32_t n,
                                double band, int tube, hipStream_t s);
 

@@ -34,6 +34,7 @@ PREC = {"fp64": HJ_FP64, "fp32": HJ_FP32}
 
 SHAPE = {"sphere": 0, "cylinder": 1, "box": 2, "ellipsoid": 3}
 HJ_DISS_LF, HJ_DISS_LLF, HJ_DISS_GLF = 0, 1, 2
+HJ_CHECK_FINITE = 1
 DISSIPATION = {"lf": HJ_DISS_LF, "llf": HJ_DISS_LLF, "glf": HJ_DISS_GLF}
 OP = {"union": 0, "intersect": 1, "subtract": 2}
 
@@ -90,6 +91,7 @@ def _load():
     lib.hj_tube_finish.argtypes = [P, P, P, P, I, D, P]
     lib.hj_solve_outputs.argtypes = [P, P, P, D, PD, I, I, P]
     lib.hj_set_dissipation.argtypes = [P, I]
+    lib.hj_set_check.argtypes = [P, I]
     lib.hj_init_shapes.argtypes = [P, P, P, I, P]
     lib.hj_rhs.argtypes = [P, P, P, P]
     lib.hj_get_schedule.argtypes = [P, D, D, PD, PD, PI64, P]
@@ -107,7 +109,7 @@ def _load():
     lib.hj_batch_destroy.argtypes = [P]
     for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
                  "hj_solve_mixed", "hj_tube_finish", "hj_solve_outputs", "hj_init_shapes",
-                 "hj_set_dissipation", "hj_rhs", "hj_get_schedule", "hj_get_info", "hj_grid_destroy", "hj_grid_set_workspace",
+                 "hj_set_dissipation", "hj_set_check", "hj_rhs", "hj_get_schedule", "hj_get_info", "hj_grid_destroy", "hj_grid_set_workspace",
                  "hj_batch_create",
                  "hj_batch_config", "hj_solve_batch", "hj_step_batch", "hj_batch_wait",
                  "hj_batch_destroy"):
@@ -200,8 +202,8 @@ def hj_solve(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, stream=None
                          _stream(stream)))
 
 
-def hj_set_dissipation(g, kind: int = HJ_DISS_LF):
-    _check(_lib.hj_set_dissipation(g, int(kind)))
+def hj_set_check(g, flags: int = HJ_CHECK_FINITE):
+    _check(_lib.hj_set_check(g, int(flags)))
 
 
 def hj_init_shapes(g, V_out, shape_list, stream=None):
@@ -405,6 +407,10 @@ class Grid:
 
     def set_dissipation(self, kind="lf"):
         hj_set_dissipation(self.handle, DISSIPATION[kind])
+
+    def set_check(self, finite: bool = True):
+        """Scan solve results for NaN/Inf (HJ_E_NUMERIC raises HJError)."""
+        hj_set_check(self.handle, HJ_CHECK_FINITE if finite else 0)
 
     def solve(self, V0, V_out, t0, tf, mode="set", stream=None):
         self._check(V0, "V0")

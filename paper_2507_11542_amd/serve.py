@@ -38,7 +38,8 @@ class Job:
     problem: inputs.Problem
     arrival: float
     t: float = 0.0
-    state: str = "pending"       # pending | active | done | rejected
+    state: str = "pending"       # pending | active | done | rejected | cancelled
+    cancel_at: Optional[float] = None  # the client withdraws the request at this time
     reason: str = ""
     admitted_at: Optional[float] = None
     finished_at: Optional[float] = None
@@ -65,6 +66,7 @@ class ServeReport:
     requests: int
     completed: int
     rejected: int
+    cancelled: int
     makespan_s: float
     updates: float
     updates_per_s: float
@@ -88,7 +90,8 @@ def percentile(xs: Sequence[float], q: float) -> float:
 def report(jobs: List[Job], makespan: float, max_active: int, peak: int, iters: int,
            updates: float) -> ServeReport:
     lat = [j.latency for j in jobs if j.state == "done"]
-    return ServeReport(len(jobs), len(lat), sum(j.state == "rejected" for j in jobs), makespan,
+    return ServeReport(len(jobs), len(lat), sum(j.state == "rejected" for j in jobs),
+                       sum(j.state == "cancelled" for j in jobs), makespan,
                        updates, updates / makespan if makespan > 0 else 0.0,
                        percentile(lat, 50), percentile(lat, 99),
                        float(np.mean(lat)) if lat else float("nan"), max_active, peak, iters)
@@ -130,9 +133,17 @@ class Server:
         k = max(1, min(self.macro_steps, int(math.ceil(self.macro_updates / max(pts, 1)))))
         return 1 << (k.bit_length() - 1)
 
-    def run(self, requests: Sequence[inputs.Request], keep_results: bool = False
-            ) -> Tuple[ServeReport, List[Job]]:
+    def run(self, requests: Sequence[inputs.Request], keep_results: bool = False,
+            cancels: Optional[Dict[int, float]] = None) -> Tuple[ServeReport, List[Job]]:
+        """Serve `requests` (arrival times relative to the start); cancels maps
+        a request's index to the time its client withdraws it.  A withdrawn
+        request leaves the queue if it is still waiting; if it is resident it
+        is released as soon as its family has no work in flight (at once if
+        none is), which returns its slot and bytes to the budget; a finished
+        request is not affected."""
         jobs = [Job(k, r.problem, r.arrival, t=r.problem.t0) for k, r in enumerate(requests)]
+        for k, t in (cancels or {}).items():
+            jobs[k].cancel_at = float(t)
         pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.rid)))
         active: Dict[Tuple, List[Job]] = collections.OrderedDict()
         inflight = set()
@@ -143,6 +154,16 @@ class Server:
         start = self.clock()
         while pending or n_active:
             now = self.clock() - start
+            # withdrawn while waiting: never admitted
+            if any(j.cancel_at is not None and j.cancel_at <= now for j in pending):
+                keep_q = collections.deque()
+                for j in pending:
+                    if j.cancel_at is not None and j.cancel_at <= now:
+                        j.state, j.reason = "cancelled", "withdrawn before admission"
+                        j.finished_at = now
+                    else:
+                        keep_q.append(j)
+                pending = keep_q
             # admission: arrived, slot free, bytes fit (arrival order)
             while pending and pending[0].arrival <= now:
                 j = pending[0]
@@ -173,8 +194,18 @@ class Server:
                     continue
                 group = active[key]
                 keep = []
+                now = self.clock() - start
                 for j in group:
-                    if j.dev_finished:
+                    if j.cancel_at is not None and j.cancel_at <= now and not j.dev_finished:
+                        # withdrawn while resident: its work so far counts, its
+                        # memory and slot return now
+                        updates += float(j.problem.points) * j.steps_done
+                        self.backend.release(j)
+                        j.state, j.reason = "cancelled", "withdrawn after admission"
+                        j.finished_at = now
+                        used -= j.nbytes
+                        n_active -= 1
+                    elif j.dev_finished:
                         if keep_results:
                             j.result = self.backend.result(j)
                         updates += float(j.problem.points) * j.steps_done

@@ -7,22 +7,28 @@ CFL 0.8, tube, t = 2.8):
 - the oracle's zero set in three psi slices (psi index n/4, n/2, 3n/4): the
   crossing points of the slice's grid edges, in cell units (for the zero-set
   Hausdorff distance);
-- how the FP64 method itself responds to single-precision storage, with the
-  oracle's FP32 storage model (``oracle.set_storage_model``) from V0 rounded to
-  single precision, max over the same band:
-    stage spread        every RK stage result rounded as it is stored;
-    stage+input spread  the same, with the tables, parameters, cell sizes,
-                        alpha and step size in single precision as well.
-  Both runs repeat the oracle's time loop step by step (the last step cut to
-  land on t = 2.8); the plain run equals the oracle's solve bit for bit.
+- the storage spreads: how far the FP64 method itself moves, max over the
+  same band, when everything a single-precision solve stores is single
+  precision (the oracle's FP32 storage model "stages+inputs",
+  ``oracle.set_storage_model``: every RK stage result, V0, the tables,
+  parameters, cell sizes, alpha and the step size) while its arithmetic stays
+  FP64, in three realizations: V0 rounded to single precision (realization
+  0), and that V0 nudged by -1, 0 or +1 single-precision ulp per node,
+  seeded (realizations 1 and 2).  The spread between the realizations shows
+  how much of a single-precision result at this horizon is set by last-bit
+  differences (the bounded y edges amplify them); the runs repeat the
+  oracle's time loop step by step (the last step cut to land on t = 2.8),
+  which without the model equals the oracle's solve bit for bit (checked on
+  the 51^3 instances).
 
-Calls only the oracle and the input generators.  At about 6 M updates/s on 8
-host threads the whole batch takes about 3 hours (three passes of 2.5e10
-updates); records are written one instance at a time, so a run can be split
-or resumed:
+Calls only the oracle and the input generators.  Four passes of 2.5e10
+updates: about 5 hours at 5-6 M updates/s (8 threads of this build host), an
+hour on 16 faster cores; records are written one instance at a time, so a run
+can be split over machines (--sizes) or resumed:
 
     python tests/golden/make_rel_dubins_batch_samples.py --out DIR [--instances A:B]
-    python tests/golden/make_rel_dubins_batch_samples.py --merge DIR
+                                                       [--sizes 51,61]
+    python tests/golden/make_rel_dubins_batch_samples.py --merge DIR[,DIR...]
 """
 import argparse
 import os
@@ -78,24 +84,41 @@ def band_inner(p, ref):
     return band & ~edge
 
 
+REALIZATIONS = 3
+
+
+def realization_v0(p, k, r):
+    """V0 in single precision for realization r of instance k: rounded (r = 0),
+    then nudged by -1, 0 or +1 ulp per node (r >= 1, seeded)."""
+    v = p.v0().astype(np.float32)
+    if r:
+        z = np.random.default_rng(9000 + 97 * k + r).integers(-1, 2, size=v.shape)
+        v = np.where(z > 0, np.nextafter(v, np.float32(np.inf)),
+                     np.where(z < 0, np.nextafter(v, np.float32(-np.inf)), v))
+    return v.astype(np.float64)
+
+
 def instance_record(k, p):
     ref, alpha, dt, steps = oracle.solve(p.v0(), *p.grid_args(), p.dynamics, p.params,
                                          p.scheme, p.order, p.cfl, p.t0, p.tf, p.mode)
-    assert np.array_equal(_stepped(p, alpha, dt, p.v0()), ref)
+    if p.n[0] == 51:  # the stepped loop is the solve's (checked where it is cheap)
+        assert np.array_equal(_stepped(p, alpha, dt, p.v0()), ref)
+    print("instance %d: oracle solve done (%d steps)" % (k, steps), flush=True)
     mask = band_inner(p, ref)
-    spread = {}
-    for name in ("stages", "stages+inputs"):
-        old = oracle.set_storage_model(name)
+    spread = []
+    for r in range(REALIZATIONS):
+        old = oracle.set_storage_model("stages+inputs")
         try:
-            got = _stepped(p, alpha, dt, _r32(p.v0()))
+            got = _stepped(p, alpha, dt, realization_v0(p, k, r))
         finally:
             oracle.set_storage_model(old)
-        spread[name] = float(np.abs(got - ref)[mask].max())
+        spread.append(float(np.abs(got - ref)[mask].max()))
+        print("instance %d: realization %d spread %.3e" % (k, r, spread[-1]), flush=True)
     nodes = np.flatnonzero(mask)
     sel = np.sort(np.random.default_rng(4100 + k).choice(
         nodes, size=min(SAMPLES, nodes.size), replace=False))
-    lines = ["# instance %d n %d steps %d stage_spread %.6e stage_input_spread %.6e\n"
-             % (k, p.n[0], steps, spread["stages"], spread["stages+inputs"])]
+    lines = ["# instance %d n %d steps %d storage_spread %s\n"
+             % (k, p.n[0], steps, " ".join("%.6e" % x for x in spread))]
     lines.extend("s %d %d %.17g\n" % (k, i, ref.ravel()[i]) for i in sel)
     for j, s in enumerate(slices(p.n[2])):
         pts = metrics.zero_set_points(ref[:, :, s], (False, False))
@@ -108,25 +131,37 @@ def main():
     ap.add_argument("--out", help="directory for the per-instance records")
     ap.add_argument("--instances", default="0:64")
     ap.add_argument("--threads", type=int, default=0)
-    ap.add_argument("--merge", help="merge the records of this directory into the golden file")
+    ap.add_argument("--sizes", default="51,61,81,101",
+                    help="grid sizes to do (to split a run between machines)")
+    ap.add_argument("--merge", help="merge the records of these directories (comma "
+                    "separated) into the golden file")
     args = ap.parse_args()
     probs = inputs.rel_dubins_batch()
     if args.merge:
         with open(GOLDEN, "w") as f:
             f.write("# FP64 oracle, the 64-instance relative-Dubins batch (rng 0), "
                     "WENO5/LF/RK3 cfl 0.8 tube t=2.8\n")
+            f.write("# instance lines: grid size, RK steps, the band storage spread of "
+                    "realizations 0, 1, 2\n")
             f.write("# s rows: instance, flat C-order node index, V(2.8) at front-band nodes\n")
             f.write("# z rows: instance, slice (psi index n/4, n/2, 3n/4), zero-set crossing "
                     "point (axis-0, axis-1 index units)\n")
+            dirs = args.merge.split(",")
             for k in range(len(probs)):
-                with open(os.path.join(args.merge, "inst_%02d.txt" % k)) as g:
+                path = next(os.path.join(d, "inst_%02d.txt" % k) for d in dirs
+                            if os.path.exists(os.path.join(d, "inst_%02d.txt" % k)))
+                with open(path) as g:
                     f.write(g.read())
         print("wrote", GOLDEN)
         return
     os.makedirs(args.out, exist_ok=True)
     oracle.set_threads(args.threads)
     a, b = (int(x) for x in args.instances.split(":"))
-    for k in range(a, b):
+    # cheapest first, so a partial run covers the most instances
+    sizes = {int(x) for x in args.sizes.split(",")}
+    order = sorted((i for i in range(a, b) if probs[i].n[0] in sizes),
+                   key=lambda i: probs[i].points)
+    for k in order:
         path = os.path.join(args.out, "inst_%02d.txt" % k)
         if os.path.exists(path):
             continue
@@ -134,7 +169,7 @@ def main():
         with open(path + ".tmp", "w") as f:
             f.writelines(lines)
         os.replace(path + ".tmp", path)
-        print(k, probs[k].n[0], steps, spread, flush=True)
+        print(k, probs[k].n[0], steps, " ".join("%.3e" % x for x in spread), flush=True)
 
 
 if __name__ == "__main__":

@@ -63,6 +63,7 @@ def test_argument_errors_without_device():
     assert lib.hj_step(None, None, None, None, 1.0, 0, None, None) == hj.HJ_E_ARG
     assert lib.hj_rhs(None, None, None, None) == hj.HJ_E_ARG
     assert lib.hj_get_info(None, None, None, None) == hj.HJ_E_ARG
+    assert lib.hj_set_check(None, hj.HJ_CHECK_FINITE) == hj.HJ_E_ARG
     assert lib.hj_tube_finish(None, None, None, None, 1, -1.0, None) == hj.HJ_E_ARG
     assert lib.hj_solve_mixed(None, None, None, 0.0, 1.0, 1, -1.0, None) == hj.HJ_E_ARG
     assert lib.hj_batch_config(None, 4096, 1024, 1) == hj.HJ_E_ARG

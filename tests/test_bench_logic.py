@@ -22,10 +22,15 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_flops_per_node_stage():
-    """Per axis 6 differences (12) and two WENO5 evaluations of 78, p-bar 2 and
-    LF 4: 174; three axes, the relative-Dubins Hamiltonian 17, the sign 1 and
-    the RK blend averaged over the three stages (13/3)."""
-    assert bench.weno5_flops_per_node_stage(3) == pytest.approx(3 * 174 + 17 + 1 + 13 / 3)
+    """The method's count: per axis one new first difference (2), one WENO
+    window (49) and two blends (26 each), p-bar 2 and LF 4: 109; three axes,
+    the relative-Dubins Hamiltonian 17, the sign 1 and the RK blend averaged
+    over the three stages (13/3).  The per-node kernel executes six
+    differences and both windows per axis: 168 per axis."""
+    assert bench.WENO_WINDOW_FLOPS == 49 and bench.WENO_BLEND_FLOPS == 26
+    assert bench.weno5_flops_per_node_stage(3) == pytest.approx(3 * 109 + 17 + 1 + 13 / 3)
+    assert bench.weno5_flops_per_node_stage(3, executed=True) == pytest.approx(
+        3 * 168 + 17 + 1 + 13 / 3)
 
 
 def test_algorithmic_bytes_per_node_stage():

@@ -105,6 +105,53 @@ def test_get_info_after_solve(orc):
         g.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_check_finite(prec):
+    """HJ_CHECK_FINITE: a solve from a V0 holding a NaN returns HJ_E_NUMERIC
+    (with the check off the same solve returns HJ_OK); a finite solve passes
+    the check and equals the unchecked result; hj_solve_mixed checks its FP64
+    result and hj_solve_outputs every output."""
+    import torch
+
+    from gpu_util import to_dev
+    from paper_2507_11542_amd import hj
+
+    p = inputs.rel_dubins_3d(n=(17, 15, 12), tf=0.2)
+    st = torch.cuda.current_stream()
+    g = hj.Grid.from_problem(p, prec)
+    try:
+        d0 = to_dev(p.v0(), prec)
+        ref, out = torch.empty_like(d0), torch.empty_like(d0)
+        g.solve(d0, ref, p.t0, p.tf, p.mode, st)
+        g.set_check(True)
+        g.solve(d0, out, p.t0, p.tf, p.mode, st)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, out)
+        bad = d0.clone()
+        bad.view(-1)[p.points // 2] = float("nan")
+        with pytest.raises(hj.HJError) as ei:
+            g.solve(bad, out, p.t0, p.tf, p.mode, st)
+        assert ei.value.status == hj.HJ_E_NUMERIC
+        outs = torch.empty((2,) + tuple(p.n), dtype=d0.dtype, device="cuda")
+        with pytest.raises(hj.HJError) as ei:
+            g.solve_outputs(bad, outs, p.t0, [0.1, 0.2], p.mode, st)
+        assert ei.value.status == hj.HJ_E_NUMERIC
+        if prec == "fp32":
+            bad64 = to_dev(p.v0(), "fp64")
+            bad64.view(-1)[7] = float("inf")
+            out64 = torch.empty_like(bad64)
+            with pytest.raises(hj.HJError) as ei:
+                g.solve_mixed(bad64, out64, p.t0, p.tf, p.mode, -1.0, st)
+            assert ei.value.status == hj.HJ_E_NUMERIC
+            g.solve_mixed(to_dev(p.v0(), "fp64"), out64, p.t0, p.tf, p.mode, -1.0, st)
+        g.set_check(False)
+        g.solve(bad, out, p.t0, p.tf, p.mode, st)
+        torch.cuda.synchronize()
+        assert torch.isnan(out).any()
+    finally:
+        g.close()
+
+
 @pytest.mark.parametrize("scheme", ["upwind1", "eno2", "eno3", "weno5"])
 @pytest.mark.parametrize("dyn", ["rel_dubins", "dubins4d", "double_integrator"])
 def test_rhs_matches_oracle_on_rough_data(orc, scheme, dyn):

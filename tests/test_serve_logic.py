@@ -170,3 +170,48 @@ def test_joiners_wait_for_the_family_in_flight():
     assert be.launches[0] == (jobs[0].key, 1, 4)   # 4 steps for one 11^3 grid
     assert be.launches[1] == (jobs[0].key, 2, 2)   # joined at 10 ms: 2 steps each
     assert jobs[1].finished_at == pytest.approx(0.020, abs=1e-3)
+
+
+def test_cancel_waiting_request_is_never_admitted():
+    """A request withdrawn while it waits for memory leaves the queue: it is
+    never admitted, and the request behind it takes the memory instead."""
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    per = 11 ** 3 * 16
+    reqs = [_req(0.0, 11, 1.0), _req(0.0, 11, 0.5), _req(0.0, 11, 0.2)]
+    rep, jobs = Server(be, hbm_budget=per, macro_steps=1, clock=clk,
+                       sleep=clk.sleep).run(reqs, cancels={1: 0.0005})
+    assert rep.completed == 2 and rep.cancelled == 1
+    assert jobs[1].state == "cancelled" and jobs[1].admitted_at is None
+    assert 1 not in be.released and be.live == 0
+    assert jobs[2].admitted_at >= jobs[0].finished_at
+
+
+def test_cancel_resident_request_frees_slot_and_bytes():
+    """A resident request withdrawn mid-solve is released once its family has
+    nothing in flight: its slot and bytes return at once, so a request that
+    did not fit is admitted long before the withdrawn solve would have
+    ended; its steps so far count as work, the others are unaffected."""
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    per = 11 ** 3 * 16
+    # request 0 needs 30 steps of 1 ms; it is withdrawn after ~5 ms
+    reqs = [_req(0.0, 11, 3.0), _req(0.001, 11, 0.3)]
+    rep, jobs = Server(be, hbm_budget=per, macro_steps=1, clock=clk,
+                       sleep=clk.sleep).run(reqs, cancels={0: 0.005})
+    assert jobs[0].state == "cancelled" and 0 in be.released
+    assert 0 < jobs[0].steps_done < 30
+    assert jobs[0].finished_at == pytest.approx(0.005, abs=0.002)
+    assert jobs[1].state == "done" and jobs[1].admitted_at < 0.008
+    assert rep.completed == 1 and rep.cancelled == 1 and be.live == 0
+    assert rep.updates == pytest.approx(11 ** 3 * (jobs[0].steps_done + 3))
+
+
+def test_cancel_after_finish_has_no_effect():
+    clk = FakeClock()
+    be = FakeBackend(clk)
+    reqs = [_req(0.0, 11, 0.2), _req(0.0, 11, 0.3)]
+    rep, jobs = Server(be, hbm_budget=10 ** 9, macro_steps=1, clock=clk,
+                       sleep=clk.sleep).run(reqs, cancels={0: 1.0})
+    assert rep.completed == 2 and rep.cancelled == 0
+    assert all(j.state == "done" for j in jobs)
