@@ -37,7 +37,17 @@ extern "C" {
 
 typedef struct hj_grid_s *hj_grid_t;
 
-typedef enum {
+/* The enums below are 32-bit integers at the boundary.  Compiled as C++ they
+ * get int32_t as their fixed underlying type, so that a caller passing a
+ * value outside the listed ones (which the calls reject with HJ_E_ARG) hands
+ * the library a valid value of the type, not undefined behaviour. */
+#ifdef __cplusplus
+#define HJ_ENUM enum : int32_t
+#else
+#define HJ_ENUM enum
+#endif
+
+typedef HJ_ENUM {
     HJ_OK = 0,
     HJ_E_ARG = -1,         /* invalid argument (message says which) */
     HJ_E_OOM = -2,         /* device or host allocation failed */
@@ -48,7 +58,7 @@ typedef enum {
 } hj_status;
 
 /* HJ_FP32 stores and computes V in float; alpha, dt and t stay double. */
-typedef enum { HJ_FP64 = 0, HJ_FP32 = 1 } hj_precision;
+typedef HJ_ENUM { HJ_FP64 = 0, HJ_FP32 = 1 } hj_precision;
 
 /* HJ_SET: the reachable set V(tf).  HJ_TUBE: the tube, V <- min(V, V0) after
  * every full step (Sec. 6.1, backward reachable tube).  HJ_TUBE_VI: the tube
@@ -57,12 +67,12 @@ typedef enum { HJ_FP64 = 0, HJ_FP32 = 1 } hj_precision;
  * only grows; V0 is not read after the start.  HJ_TUBE_OUTPUTS: V <- min(V, V0)
  * at the output times only (hj_solve: at tf; hj_solve_outputs: at each
  * output time), free steps in between. */
-typedef enum { HJ_SET = 0, HJ_TUBE = 1, HJ_TUBE_VI = 2, HJ_TUBE_OUTPUTS = 3 } hj_mode;
+typedef HJ_ENUM { HJ_SET = 0, HJ_TUBE = 1, HJ_TUBE_VI = 2, HJ_TUBE_OUTPUTS = 3 } hj_mode;
 
 /* One-sided derivative approximations (Sec. 3): first order (Sec. 3.1, halo
  * 1), ENO2 (Sec. 3.2, halo 2), ENO3 (Sec. 3.2's third-order paragraph, halo
  * 3), WENO5 (Sec. 3.3, halo 3). */
-typedef enum { HJ_UPWIND1 = 1, HJ_ENO2 = 2, HJ_ENO3 = 3, HJ_WENO5 = 5 } hj_space;
+typedef HJ_ENUM { HJ_UPWIND1 = 1, HJ_ENO2 = 2, HJ_ENO3 = 3, HJ_WENO5 = 5 } hj_space;
 
 /* Lax-Friedrichs dissipation coefficients (Sec. 4; its dissipation routine
  * takes the one-sided derivatives).  HJ_DISS_LF (default): alpha_d = max over
@@ -73,10 +83,10 @@ typedef enum { HJ_UPWIND1 = 1, HJ_ENO2 = 2, HJ_ENO3 = 3, HJ_WENO5 = 5 } hj_space
  * extra reduction pass over the grid per stage).  A switching function's
  * sign set over a box comes from interval arithmetic on its ends.  The step
  * size always uses the control-set bound, which bounds both box variants. */
-typedef enum { HJ_DISS_LF = 0, HJ_DISS_LLF = 1, HJ_DISS_GLF = 2 } hj_dissipation;
+typedef HJ_ENUM { HJ_DISS_LF = 0, HJ_DISS_LLF = 1, HJ_DISS_GLF = 2 } hj_dissipation;
 
 /* TVD Runge-Kutta order (Sec. 5): forward Euler, Shu-Osher RK2, RK3. */
-typedef enum { HJ_RK1 = 1, HJ_RK2 = 2, HJ_RK3 = 3 } hj_time;
+typedef HJ_ENUM { HJ_RK1 = 1, HJ_RK2 = 2, HJ_RK3 = 3 } hj_time;
 
 /* Compiled dynamics, sign convention V_t + H = 0, H = -opt_{u,d} p.f(x,u,d).
  * params (in order) and dimension:
@@ -96,7 +106,7 @@ typedef enum { HJ_RK1 = 1, HJ_RK2 = 2, HJ_RK3 = 3 } hj_time;
  *                                       maximises, pursuer (up) minimises:
  *                                       H = -a p1 cos th - p2 (a sin th + a - g)
  *                                           - umax|p1 x - p3| + umax|p2 x + p3| */
-typedef enum {
+typedef HJ_ENUM {
     HJ_DYN_TRANSLATION = 0,
     HJ_DYN_BALL = 1,
     HJ_DYN_DOUBLE_INTEGRATOR = 2,
@@ -118,13 +128,13 @@ typedef enum {
  * Shapes combine left to right with their op (the first one's is ignored):
  * HJ_OP_UNION min(v, s), HJ_OP_INTERSECT max(v, s), HJ_OP_SUBTRACT
  * max(v, -s). */
-typedef enum {
+typedef HJ_ENUM {
     HJ_SHAPE_SPHERE = 0,
     HJ_SHAPE_CYLINDER = 1,
     HJ_SHAPE_BOX = 2,
     HJ_SHAPE_ELLIPSOID = 3
 } hj_shape_kind;
-typedef enum { HJ_OP_UNION = 0, HJ_OP_INTERSECT = 1, HJ_OP_SUBTRACT = 2 } hj_shape_op;
+typedef HJ_ENUM { HJ_OP_UNION = 0, HJ_OP_INTERSECT = 1, HJ_OP_SUBTRACT = 2 } hj_shape_op;
 typedef struct {
     int32_t kind;      /* hj_shape_kind */
     int32_t op;        /* hj_shape_op */

@@ -13,7 +13,9 @@ import os
 from typing import Optional, Sequence, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhj.so")
+# HJ_LIB_PATH: another build of the same library (the host-sanitizer tests
+# load one); the default is the in-tree build
+LIB_PATH = os.environ.get("HJ_LIB_PATH") or os.path.join(_HERE, "libhj.so")
 
 # enum values of include/hj.h
 HJ_OK, HJ_E_ARG, HJ_E_OOM, HJ_E_DEVICE, HJ_E_STATE, HJ_E_NUMERIC, HJ_E_UNSUPPORTED = \
