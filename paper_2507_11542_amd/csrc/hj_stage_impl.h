@@ -534,7 +534,9 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
         }
     }
     if (a.tube) val = fmin(val, global_ptr(a.v0)[node]);
-    global_ptr(a.out)[node] = val;
+    // a streaming store: nothing in this launch reads the output again (the
+    // next stage is another launch, on any XCD); measured 1-3 % faster
+    __builtin_nontemporal_store(val, &global_ptr(a.out)[node]);
 }
 
 // Occupancy floor of the per-node kernel: the 3-D FP64 WENO5 kernels fit 80

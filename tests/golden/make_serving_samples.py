@@ -48,15 +48,21 @@ def picked(base):
 
 
 def _stepped(p, alpha, dt, v0):
-    """The oracle's time loop one step at a time from v0 (the storage model
-    set by the caller applies to each step)."""
-    v = v0.copy()
+    """The oracle's time loop from v0 (the storage model set by the caller
+    applies to every step): its full steps of dt in one call and the last,
+    cut to land on tf, in another (the same step sizes as the loop)."""
     t, eps = p.t0, 100.0 * 2.220446049250313e-16
+    hs = []
     while p.tf - t >= eps * (p.tf - p.t0):
         h = dt if dt < p.tf - t else p.tf - t
-        v = oracle.steps(v, v0, *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
-                         alpha, h, 1, mode=p.mode)
+        hs.append(h)
         t = t + h
+    full = len(hs) if hs and hs[-1] == dt else len(hs) - 1
+    v = v0.copy()
+    for h, k in ((dt, full), (hs[-1] if hs else dt, len(hs) - full)):
+        if k:
+            v = oracle.steps(v, v0, *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
+                             alpha, h, k, mode=p.mode)
     return v
 
 
