@@ -176,6 +176,22 @@ hj_status hj_set_dissipation(hj_grid_t g, hj_dissipation kind);
 hj_status hj_solve(hj_grid_t g, const void *V0, void *V_out, double t0, double tf,
                    hj_mode mode, void *hip_stream);
 
+/* hj_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, checks, kernels and results as hj_solve, but the RK stage
+ * buffers are taken from a static 128 MiB device array of the library (one
+ * per device, held until the process ends) instead of the handle's own, and
+ * the call allocates nothing.  The stage buffers of RK3 need 2 * prod(N) *
+ * sizeof(element) bytes (RK1/RK2: half), so FP64 grids up to 8,388,608 nodes
+ * and FP32 grids up to 16,777,216 nodes fit; larger grids get HJ_E_ARG.
+ * HJ_DISS_GLF (per-stage reduction buffers) gets HJ_E_UNSUPPORTED.  The array
+ * is shared by every call on a device and keeps the last call's contents:
+ * calls whose work overlaps on one device (other streams, other threads)
+ * race, so order them on one stream or wait between them.  Like hj_solve it
+ * waits once on the stream for alpha. */
+hj_status hj_solve_noalloc(hj_grid_t g, const void *V0, void *V_out, double t0, double tf,
+                           hj_mode mode, void *hip_stream);
+
 /* Sec. 2.2: V_out (device, prod(N) elements of the grid's precision) at every
  * node from the nshapes shapes (host array, 1..16 of them), evaluated in FP64
  * on the device (FP32 grids store the rounded value), so a solve's initial
@@ -317,12 +333,13 @@ hj_status hj_batch_wait(hj_batch_t b, void *hip_stream, double *t_final, int64_t
 hj_status hj_batch_destroy(hj_batch_t b);
 
 /* Optional check of solve results: with HJ_CHECK_FINITE set, hj_solve,
- * hj_solve_outputs and hj_solve_mixed scan their result on
+ * hj_solve_outputs, hj_solve_mixed and hj_solve_noalloc scan their result on
  * the device for NaN or infinite values after the last stage, wait for the
  * stream, and return HJ_E_NUMERIC if any is found (the result is written
  * either way).  Off by default: a solve then returns after enqueueing.
- * hj_step and batches are not checked.  Enabling it allocates a device flag.
- * HJ_E_ARG on unknown flags. */
+ * hj_step and batches are not checked.  Enabling it allocates a device flag
+ * (hj_solve_noalloc stays allocation-free once it is enabled).  HJ_E_ARG on
+ * unknown flags. */
 enum { HJ_CHECK_FINITE = 1 };
 hj_status hj_set_check(hj_grid_t g, int flags);
 

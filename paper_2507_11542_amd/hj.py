@@ -88,6 +88,7 @@ def _load():
     lib.hj_set_dynamics.argtypes = [P, I, PD, I]
     lib.hj_set_scheme.argtypes = [P, I, I, D]
     lib.hj_solve.argtypes = [P, P, P, D, D, I, P]
+    lib.hj_solve_noalloc.argtypes = [P, P, P, D, D, I, P]
     lib.hj_step.argtypes = [P, P, P, PD, D, I, PD, P]
     lib.hj_solve_mixed.argtypes = [P, P, P, D, D, I, D, P]
     lib.hj_tube_finish.argtypes = [P, P, P, P, I, D, P]
@@ -109,7 +110,8 @@ def _load():
                                   ctypes.POINTER(I), P]
     lib.hj_batch_wait.argtypes = [P, P, PD, PI64]
     lib.hj_batch_destroy.argtypes = [P]
-    for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve", "hj_step",
+    for name in ("hj_grid_create", "hj_set_dynamics", "hj_set_scheme", "hj_solve",
+                 "hj_solve_noalloc", "hj_step",
                  "hj_solve_mixed", "hj_tube_finish", "hj_solve_outputs", "hj_init_shapes",
                  "hj_set_dissipation", "hj_set_check", "hj_rhs", "hj_get_schedule", "hj_get_info", "hj_grid_destroy", "hj_grid_set_workspace",
                  "hj_batch_create",
@@ -202,6 +204,15 @@ def hj_set_scheme(g, space: int = HJ_WENO5, time: int = HJ_RK3, cfl: float = 0.8
 def hj_solve(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, stream=None):
     _check(_lib.hj_solve(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
                          _stream(stream)))
+
+
+def hj_solve_noalloc(g, V0, V_out, t0: float, tf: float, mode: int = HJ_SET, stream=None):
+    _check(_lib.hj_solve_noalloc(g, _ptr(V0), _ptr(V_out), float(t0), float(tf), int(mode),
+                                 _stream(stream)))
+
+
+def hj_set_dissipation(g, kind: int = HJ_DISS_LF):
+    _check(_lib.hj_set_dissipation(g, int(kind)))
 
 
 def hj_set_check(g, flags: int = HJ_CHECK_FINITE):
@@ -418,6 +429,12 @@ class Grid:
         self._check(V0, "V0")
         self._check(V_out, "V_out")
         hj_solve(self.handle, V0, V_out, t0, tf, MODE[mode], stream)
+
+    def solve_noalloc(self, V0, V_out, t0, tf, mode="set", stream=None):
+        """hj_solve with the stage buffers in the library's static scratch."""
+        self._check(V0, "V0")
+        self._check(V_out, "V_out")
+        hj_solve_noalloc(self.handle, V0, V_out, t0, tf, MODE[mode], stream)
 
     def init_shapes(self, V_out, shape_list, stream=None):
         """V_out <- the implicit surface of shape_list (dicts as in make_shapes)."""

@@ -55,6 +55,7 @@ def test_argument_errors_without_device():
     assert lib.hj_set_dynamics(None, 0, None, 0) == hj.HJ_E_ARG
     assert lib.hj_set_scheme(None, 5, 3, 0.8) == hj.HJ_E_ARG
     assert lib.hj_solve(None, None, None, 0.0, 1.0, 0, None) == hj.HJ_E_ARG
+    assert lib.hj_solve_noalloc(None, None, None, 0.0, 1.0, 0, None) == hj.HJ_E_ARG
     ts = (ctypes.c_double * 2)(0.5, 1.0)
     assert lib.hj_solve_outputs(None, None, None, 0.0, ts, 2, 0, None) == hj.HJ_E_ARG
     shp = hj.make_shapes([dict(kind="sphere", radius=1.0)])
