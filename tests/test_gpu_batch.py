@@ -1,8 +1,12 @@
-"""Batched solves (hj_solve_batch, one fused launch per RK-stage round) against plain solves and the
-oracle: every instance of an uneven batch equals its own hj_solve bit for bit
-(same per-node arithmetic, same FP64 step sizes, device-accumulated time) and
-matches the FP64 oracle at 1e-12."""
+"""Batched solves (hj_solve_batch, one fused launch per RK-stage round)
+against plain solves and the oracle: every instance of an uneven batch equals
+its own hj_solve bit for bit (same per-node arithmetic, same FP64 step sizes,
+device-accumulated time) and matches the FP64 oracle at 1e-12 in FP64; every
+instance of the 64-instance benchmark batch is checked against the FP64
+oracle in FP32, over two steps from the oracle's own state and over the full
+horizon."""
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -224,44 +228,75 @@ def test_batch_rejects_shared_stage_buffers():
         b.close()
 
 
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rel_dubins_batch_samples.txt")
+
+
 def _batch_golden():
-    """Stored FP64-oracle front-band values of the batch's 51^3 instances and
-    the oracle's own spread under FP32-sized rounding of its state, keyed by
-    instance."""
-    path = os.path.join(os.path.dirname(__file__), "golden", "rel_dubins_batch_51_samples.txt")
-    spread, rows = {}, []
-    with open(path) as f:
+    """Stored FP64-oracle values of the 64-instance batch: per instance the
+    band storage spreads of three FP32-storage realizations, front-band
+    samples (instance, node, value) and the zero set's crossing points in
+    three psi slices (instance, slice, axis-0, axis-1)."""
+    spread, samples, zeros = {}, [], []
+    with open(GOLDEN) as f:
         for line in f:
-            if line.startswith("# instance"):
-                w = line.split()
-                spread[int(w[2])] = (float(w[8]), float(w[10]))
-            elif not line.startswith("#"):
-                rows.append(line.split())
-    data = np.array(rows, dtype=np.float64)
-    return spread, data
+            w = line.split()
+            if line.startswith("# instance") and w[2].isdigit():
+                spread[int(w[2])] = [float(x) for x in w[w.index("storage_spread") + 1:]]
+            elif w and w[0] == "s":
+                samples.append([float(x) for x in w[1:]])
+            elif w and w[0] == "z":
+                zeros.append([float(x) for x in w[1:]])
+    return spread, np.array(samples), np.array(zeros)
 
 
-def test_full_batch_config_instances_vs_oracle(orc):
+def _slice_hausdorff(v, zeros_k, n):
+    """Largest of the zero-set Hausdorff distances (cells) of the three psi
+    slices of v against the oracle's stored crossing points (rows: instance,
+    slice, axis-0, axis-1)."""
+    from scipy.spatial import cKDTree
+
+    from make_rel_dubins_batch_samples import slices
+    from paper_2507_11542_amd import metrics
+
+    worst = 0.0
+    for j, sidx in enumerate(slices(n)):
+        ref = zeros_k[zeros_k[:, 1] == j][:, 2:]
+        got = metrics.zero_set_points(v[:, :, sidx], (False, False))
+        if len(ref) == 0 and len(got) == 0:
+            continue
+        assert len(ref) and len(got), "zero set present on one side only"
+        d1, _ = cKDTree(ref).query(got)
+        d2, _ = cKDTree(got).query(ref)
+        worst = max(worst, float(d1.max()), float(d2.max()))
+    return worst
+
+
+def test_full_batch_config_instances_vs_oracle():
     """The 64-instance batch of the benchmark (N in {51, 61, 81, 101}, FP32
-    bulk, FP64 time, t = 2.8) in one flat graph-replayed batch: every 8th
-    instance and the 51^3 ones equal their plain FP32 solves bit for bit; the
-    51^3 ones are checked against the FP64 oracle at stored front-band nodes
-    and, for two of them, by the zero-set Hausdorff distance (<= 0.5 cell).
+    bulk, FP64 time, t = 2.8) in one flat graph-replayed batch, every instance
+    against the FP64 oracle: front-band values at stored nodes, and the zero
+    set in three psi slices within half a cell (Hausdorff) of the oracle's;
+    every 8th instance also equals its plain FP32 solve bit for bit.
 
-    The band bar is 1e-4 or, where larger, twice the oracle's own spread: at
-    this horizon the FP64 method itself, with its state perturbed each step by
-    noise of FP32-rounding size, moves by up to a few 1e-3 in the band (the
-    tail of the set along equal headings, and fronts that reach the bounded
-    y edges), so no FP32-state solve can be held to 1e-4 there."""
+    The band bar of each instance is 1e-4, or SPREAD_BAR_FACTOR (gpu_util)
+    times the largest band spread of three FP32-storage realizations of the
+    FP64 method itself where that is larger: at this horizon the discrete
+    scheme's growing mode at the bounded y edges (e-folding in about 20 steps)
+    amplifies last-bit differences of the stored state, so the method with
+    FP64 arithmetic and single-precision storage lands anywhere in that spread
+    depending on which last bits its V0 has; no single-precision solve can be
+    held closer than that."""
     import json
 
     import torch
 
-    from gpu_util import gpu_solve, oracle_solve, to_dev
-    from paper_2507_11542_amd import hj, metrics
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from gpu_util import SPREAD_BAR_FACTOR, gpu_solve, to_dev
+    from paper_2507_11542_amd import hj
 
-    spread, data = _batch_golden()
+    spread, samples, zeros = _batch_golden()
     probs = inputs.rel_dubins_batch()
+    assert sorted(spread) == list(range(len(probs)))
     grids = [hj.Grid.from_problem(p, "fp32") for p in probs]
     v0s = [to_dev(p.v0(), "fp32") for p in probs]
     outs = [torch.empty_like(v) for v in v0s]
@@ -276,21 +311,84 @@ def test_full_batch_config_instances_vs_oracle(orc):
         b.close()
         for g in grids:
             g.close()
-    small = sorted(spread)
-    assert small == [k for k, p in enumerate(probs) if p.n[0] == 51]
+    worst = []
     for k, p in enumerate(probs):
         got = outs[k].cpu().numpy().astype(np.float64)
-        if k % 8 == 0 or k in small:
+        if k % 8 == 0:
             assert np.array_equal(got, gpu_solve(p, "fp32")), k
-        if k in small:
-            rows = data[data[:, 0] == k]
-            band_err = float(np.abs(got.ravel()[rows[:, 1].astype(np.int64)] - rows[:, 2]).max())
-            bar = max(1e-4, 2.0 * spread[k][1])
-            rec = {"instance": k, "band_err": band_err, "storage_spread": spread[k][0],
-                   "noise_spread": spread[k][1], "bar": bar}
-            if k in small[:2]:
-                ref, *_ = oracle_solve(orc, p)
-                rec["hausdorff_cells"] = metrics.hausdorff_cells(got, ref, p.periodic)
-                assert rec["hausdorff_cells"] <= 0.5
-            print(json.dumps(rec), flush=True)
-            assert band_err <= bar, k
+        rows = samples[samples[:, 0] == k]
+        band_err = float(np.abs(got.ravel()[rows[:, 1].astype(np.int64)] - rows[:, 2]).max())
+        bar = max(1e-4, SPREAD_BAR_FACTOR * max(spread[k]))
+        haus = _slice_hausdorff(got, zeros[zeros[:, 0] == k], p.n[2])
+        rec = {"instance": k, "n": p.n[0], "band_err": band_err, "spreads": spread[k],
+               "bar": bar, "slice_hausdorff_cells": haus}
+        print(json.dumps(rec), flush=True)
+        worst.append((band_err > bar, haus > 0.5, k))
+    assert not any(a or h for a, h, _ in worst), [k for a, h, k in worst if a or h]
+
+
+def test_batch_fp32_local_steps_vs_oracle_all_instances(orc):
+    """The FP32 arithmetic of the batched kernel, free of the long-horizon
+    amplification: every instance of the 64-instance batch starts from the
+    oracle's own state after 6 steps of the FP32 storage model (single
+    precision storage, FP64 arithmetic), and the batch (hj_step_batch) and
+    the oracle each take 2 more steps from it.  The two differ only by the
+    kernels' single-precision arithmetic: at most 8 single-precision ulps of
+    the grid's largest |V| anywhere (six stages, each result rounded once on
+    either side after arithmetic that differs by a few roundings), and 1e-6
+    in the front band (|V| < 3 max dx, where an ulp is below 1.2e-7)."""
+    import json
+
+    import torch
+
+    from gpu_util import to_dev
+    from paper_2507_11542_amd import hj
+
+    probs = inputs.rel_dubins_batch()
+    n0, n1 = 6, 2
+    starts, refs, times = [], [], []
+    old = orc.set_storage_model("stages+inputs")
+    try:
+        for p in probs:
+            alpha, dt, _, _ = orc.schedule(*p.grid_args(), p.dynamics, p.params, p.cfl, p.t0,
+                                           p.tf)
+            v0 = p.v0().astype(np.float32).astype(np.float64)
+            x = orc.steps(v0, v0, *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
+                          alpha, dt, n0, mode=p.mode)
+            y = orc.steps(x, v0, *p.grid_args(), p.dynamics, p.params, p.scheme, p.order,
+                          alpha, dt, n1, mode=p.mode)
+            t = p.t0
+            for _ in range(n0):
+                t = t + dt
+            starts.append(x)
+            refs.append(y)
+            times.append(t)
+    finally:
+        orc.set_storage_model(old)
+    grids = [hj.Grid.from_problem(p, "fp32") for p in probs]
+    v0s = [to_dev(p.v0(), "fp32") for p in probs]
+    vs = [to_dev(x, "fp32") for x in starts]
+    b = hj.Batch()
+    st = torch.cuda.current_stream()
+    try:
+        ts, taken, _ = b.step(grids, v0s, vs, [p.t0 for p in probs], times,
+                              [p.tf for p in probs], [p.mode for p in probs], n1, st)
+        b.wait(len(probs), st)
+        torch.cuda.synchronize()
+    finally:
+        b.close()
+        for g in grids:
+            g.close()
+    assert taken == [n1] * len(probs)
+    bad = []
+    for k, (p, v, y) in enumerate(zip(probs, vs, refs)):
+        got = v.cpu().numpy().astype(np.float64)
+        err = np.abs(got - y)
+        ulp = float(np.spacing(np.float32(np.abs(y).max())))
+        band = np.abs(y) < 3.0 * float(inputs.cell_sizes(*p.grid_args()).max())
+        rec = {"instance": k, "max_abs": float(err.max()), "ulps": float(err.max()) / ulp,
+               "band_max_abs": float(err[band].max())}
+        print(json.dumps(rec), flush=True)
+        if rec["ulps"] > 8 or rec["band_max_abs"] > 1e-6:
+            bad.append(k)
+    assert not bad, bad

@@ -148,39 +148,64 @@ def test_served_solo_requests_equal_alone(solo_points):
 
 
 def test_served_stream_requests_vs_oracle():
-    """The smallest request of each family of the 96-request benchmark stream,
-    served with FP64 results, against the FP64 oracle's stored values: the
-    front band within 1e-4 or, where larger, twice the oracle's own spread
-    under FP32-sized rounding of its state (both stored by
-    tests/golden/make_serving_samples.py)."""
+    """The smallest and the largest request of each family of the 256-request
+    benchmark stream, served together with FP64 results, against the FP64
+    oracle's stored values.  The front band is held to 1e-4, or where larger
+    to SPREAD_BAR_FACTOR (gpu_util) times the largest band spread of three
+    FP32-storage realizations of the oracle itself (single-precision storage, FP64 arithmetic, V0 differing
+    in its last bits; tests/golden/make_serving_samples.py): that spread is
+    how far the method moves from last-bit differences of its stored state at
+    the request's horizon, which no single-precision solve can undercut.  A
+    request whose front lies only near the bounded edges has no band; its
+    sampled nodes are held to the same rule with the realizations' spread
+    over those nodes."""
     import json
     import os
 
+    from gpu_util import SPREAD_BAR_FACTOR
     from paper_2507_11542_amd.serve import GpuBackend, Server
 
     gold = os.path.join(os.path.dirname(__file__), "golden", "serving_stream_samples.txt")
     rows = np.loadtxt(gold)
-    spread = {}
+    spread, sampled_spread = {}, {}
     with open(gold) as f:
         for line in f:
             w = line.split()
             if line.startswith("# request"):
-                spread[int(w[2])] = float(w[w.index("noise_spread") + 1])
-    base = inputs.serving_stream(count=96, rate=1.0, seed=0)
+                k = int(w[2])
+                if "sampled_spread" in w:
+                    spread[k] = None
+                    sampled_spread[k] = max(float(x) for x in w[w.index("sampled_spread") + 1:])
+                else:
+                    spread[k] = max(float(x) for x in w[w.index("storage_spread") + 1:])
+    base = inputs.serving_stream(count=256, rate=1.0, seed=0)
     ids = sorted(spread)
+    assert len(ids) == 6
     reqs = [inputs.Request(0.0, base[k].problem) for k in ids]
     be = GpuBackend(prec="fp32", device_v0=True, fp64_finish=True)
     try:
-        rep, jobs = Server(be, hbm_budget=8 << 30, macro_steps=16).run(reqs, keep_results=True)
+        rep, jobs = Server(be, hbm_budget=16 << 30, macro_steps=16).run(reqs, keep_results=True)
     finally:
         be.close()
     assert rep.completed == len(reqs)
+    bad = []
     for k, j in zip(ids, jobs):
         sel = rows[rows[:, 0] == k]
         err = np.abs(j.result.ravel()[sel[:, 1].astype(np.int64)] - sel[:, 3])
         band = sel[:, 2] == 1
-        bar = max(1e-4, 2.0 * spread[k])
-        print(json.dumps({"request": k, "family": j.problem.dynamics,
-                          "band_err": float(err[band].max()), "bar": bar}), flush=True)
-        assert band.sum() > 100
-        assert err[band].max() <= bar
+        rec = {"request": k, "family": j.problem.dynamics, "grid": list(j.problem.n),
+               "sampled_err": float(err.max()), "spread": spread[k]}
+        if spread[k] is None:
+            assert not band.any()
+            rec["spread"] = sampled_spread[k]
+            rec["bar"] = max(1e-4, SPREAD_BAR_FACTOR * sampled_spread[k])
+            ok = err.max() <= rec["bar"]
+        else:
+            assert band.sum() > 100
+            rec["band_err"] = float(err[band].max())
+            rec["bar"] = max(1e-4, SPREAD_BAR_FACTOR * spread[k])
+            ok = rec["band_err"] <= rec["bar"]
+        print(json.dumps(rec), flush=True)
+        if not ok:
+            bad.append(k)
+    assert not bad, bad
