@@ -219,6 +219,80 @@ __device__ inline void line_stencil_select(const gmem<T> *__restrict__ v, uint32
     }
 }
 
+// The same 2W+1 values along the fastest axis (stride 1) from one load per
+// node: the lanes of a wavefront hold consecutive nodes, so the neighbours at
+// offsets -W..W come from the lanes beside it (cross-lane shuffles through
+// the LDS crossbar, which spare the vector-memory address and data units
+// that the stencil loads otherwise keep busy).  A lane loads a neighbour
+// itself where the lane holding it is outside the wavefront or inactive, and
+// on a periodic axis where the neighbour wraps round the line; on a bounded
+// axis the ghosts are the linear extrapolations of line_value, from the
+// line's two end values, which lie in the node's own stencil whenever a
+// ghost is needed (every axis has at least 2W+1 nodes).
+template <typename T, int W>
+__device__ inline void line_stencil_shuffle(const gmem<T> *__restrict__ v, uint32_t node, int i,
+                                            int n, bool periodic, T *s)
+{
+    const uint64_t act = __ballot(1);
+    const int lane = int(__lane_id());
+    const uint32_t base = node - uint32_t(i);
+    const T c = v[node];
+#pragma unroll
+    for (int k = 0; k <= 2 * W; ++k) {
+        const int o = k - W;
+        if (o == 0) {
+            s[k] = c;
+            continue;
+        }
+        T x = o < 0 ? T(__shfl_up(c, unsigned(-o))) : T(__shfl_down(c, unsigned(o)));
+        const int src = lane + o;
+        const bool have = src >= 0 && src < 64 && ((act >> src) & 1u);
+        const int j = i + o;
+        const bool inside = j >= 0 && j < n;
+        if ((inside && !have) || (periodic && !inside)) {
+            const int jw = j < 0 ? j + n : (j >= n ? j - n : j);
+            x = v[base + uint32_t(jw)];
+        }
+        s[k] = x;
+    }
+    if (!periodic) {
+        // line positions 0, 1 and n-1, n-2: stencil entries W - i (+1) near
+        // the first end, W + n-1-i (-1) near the last
+        T e0 = s[W], e1 = s[W], f0 = s[W], f1 = s[W];
+#pragma unroll
+        for (int m = 0; m < W; ++m) {
+            e0 = i == m ? s[W - m] : e0;
+            e1 = i == m ? s[W - m + 1] : e1;
+            f0 = i == n - 1 - m ? s[W + m] : f0;
+            f1 = i == n - 1 - m ? s[W + m - 1] : f1;
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int j = i - W + k;
+            const T g = e0 + T(-j) * (e0 - e1);
+            s[k] = j < 0 ? g : s[k];
+        }
+#pragma unroll
+        for (int k = W + 1; k <= 2 * W; ++k) {
+            const int j = i - W + k;
+            const T g = f0 + T(j - (n - 1)) * (f0 - f1);
+            s[k] = j >= n ? g : s[k];
+        }
+    }
+}
+
+// Whether the fastest axis is gathered by cross-lane shuffles: the FP64 ENO2
+// kernels, whose time is set by the vector-memory units (counters: address
+// and data units busy about 80 % of a rockets 100^3 stage, 18 cycles per
+// 64-lane FP64 load) and which have VALU issue to spare (47 %); measured
+// 13.5 -> 11.9 us per rockets stage.  FP32 loads cost those units half as
+// much, and the shuffles, selects and edge loads made the FP32 kernel 10 %
+// slower; the WENO5 kernels are bound by VALU issue.
+template <typename T, int SCH>
+struct ShuffleFastest {
+    static constexpr bool value = SCH == kEno2 && sizeof(T) == 8;
+};
+
 // p- and p+ along one axis at one node (Sec. 3.1-3.3).
 // First divided differences use the reciprocal cell size 1/dx, second ones
 // 1/(2 dx), third ones 1/(3 dx) (all computed once on the host in FP64).
@@ -234,7 +308,10 @@ __device__ inline void axis_derivs(const gmem<T> *__restrict__ v, uint32_t node,
     T s[2 * W + 1];
     const bool interior = i >= W && i < n - W;
     if (fastest) {
-        line_stencil_select<T, W>(v, node, i, n, stride, periodic, s);
+        if constexpr (ShuffleFastest<T, SCH>::value)
+            line_stencil_shuffle<T, W>(v, node, i, n, periodic, s);
+        else
+            line_stencil_select<T, W>(v, node, i, n, stride, periodic, s);
     } else if (interior) {
 #pragma unroll
         for (int k = 0; k <= 2 * W; ++k) s[k] = v[node + (k - W) * int(stride)];
@@ -485,11 +562,15 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
     int ii[D];
     node_indices<T, D>(a, node, ii);
     T pm[D], pp[D], center = T(0);
+    // the fastest axis first where it is gathered by shuffles, so that its
+    // one load is the first in flight (measured 7 % faster than last)
 #pragma unroll
-    for (int d = 0; d < D; ++d)
+    for (int q = 0; q < D; ++q) {
+        const int d = ShuffleFastest<T, SCH>::value ? (q + D - 1) % D : q;
         axis_derivs<T, SCH>(global_ptr(a.vs), node, ii[d], int(a.n[d]), a.stride[d],
                             (a.periodic >> d) & 1u, a.dx[d], a.inv_dx[d], a.inv_2dx[d],
                             a.inv_3dx[d], pm[d], pp[d], center, d == D - 1);
+    }
     T pbar[D];
     T diss = T(0);
     if (a.diss == kLF) {

@@ -152,6 +152,25 @@ def test_check_finite(prec):
         g.close()
 
 
+@pytest.mark.parametrize("n", [(13, 5), (7, 63), (5, 64), (6, 65), (5, 130)])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_eno2_fastest_axis_across_wavefronts(orc, n, periodic):
+    """FP64 ENO2 takes its fastest-axis neighbours from the lanes beside it:
+    lines shorter than, equal to and one longer than a 64-lane wavefront, the
+    shortest line the scheme allows (5), lines spanning two wavefronts, a
+    ragged last wavefront; bounded (ghosts from the line's end values) and
+    periodic (wrapped neighbours loaded) fastest axis.  Bit for bit against
+    the oracle."""
+    from gpu_util import gpu_solve, oracle_solve
+
+    p = inputs.Problem("tr", n, (-2.0, -2.0), (2.0, 2.0), (True, periodic), "translation",
+                       (0.5, -0.75), "eno2", 2, 0.8, 0.0, 0.2, "set", radius=0.8)
+    print("case", n, periodic, flush=True)
+    ref, *_ = oracle_solve(orc, p)
+    got = gpu_solve(p, "fp64")
+    assert np.abs(got - ref).max() <= TOL64
+
+
 @pytest.mark.parametrize("scheme", ["upwind1", "eno2", "eno3", "weno5"])
 @pytest.mark.parametrize("dyn", ["rel_dubins", "dubins4d", "double_integrator"])
 def test_rhs_matches_oracle_on_rough_data(orc, scheme, dyn):
