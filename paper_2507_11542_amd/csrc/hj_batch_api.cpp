@@ -477,8 +477,14 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
         pre[k + 1] = uint32_t(next);
     }
     if ((s = reserve(b, uint32_t(n), rounds, pre[n])) != HJ_OK) return s;
-    for (int k = 0; k < n; ++k)
-        for (uint32_t t = 0; t < tiles[ord[k]]; ++t) b->h_tile_map[pre[k] + t] = {ord[k], t};
+    for (int k = 0; k < n; ++k) {
+        const uint32_t last = order * steps[ord[k]];
+        for (uint32_t t = 0; t < tiles[ord[k]]; ++t)
+            b->h_tile_map[pre[k] + t] = {ord[k], t, last, 0u};
+    }
+    // past the batch's tiles: entries that run in no round (a flat launch may
+    // have more workgroups than the round has tiles)
+    for (uint32_t e = pre[n]; e < b->cap_tiles; ++e) b->h_tile_map[e] = {0u, 0u, 0u, 0u};
     uint64_t total = 0;
     uint32_t active = uint32_t(n);
     for (uint32_t r = 0; r < rounds; ++r) {
@@ -508,7 +514,7 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
     b->h_gl->order = order;
 
     HJ_HIP(hipMemcpyAsync(b->inst, b->h_inst, isz * n, hipMemcpyHostToDevice, st), "upload");
-    HJ_HIP(hipMemcpyAsync(b->tile_map, b->h_tile_map, sizeof(TileRef) * pre[n],
+    HJ_HIP(hipMemcpyAsync(b->tile_map, b->h_tile_map, sizeof(TileRef) * b->cap_tiles,
                           hipMemcpyHostToDevice, st),
            "upload");
     HJ_HIP(hipMemcpyAsync(b->round_off, b->h_round_off, sizeof(uint32_t) * (rounds + 1),

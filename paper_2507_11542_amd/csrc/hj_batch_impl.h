@@ -39,7 +39,10 @@ struct BatchInst {
 struct TileRef {
     uint32_t inst;     // instance id (original order)
     uint32_t tile;     // tile index within the instance
+    uint32_t rounds;   // the instance runs in rounds [0, rounds); 0 past the map's tiles
+    uint32_t pad;
 };
+static_assert(sizeof(TileRef) == 16, "the round kernel reads a map entry as 4 words");
 
 struct BatchCtl {
     double t[2];       // t at the start of even / odd steps
@@ -58,8 +61,9 @@ template <typename T>
 struct BatchPtrs {
     const BatchInst<T> *inst;  // [ninst], original order
     BatchCtl *ctl;             // [ninst]
-    const TileRef *tile_map;   // [tiles of round 0] tiles of the instances by step
-                               // count, descending; round r runs a prefix of it
+    const TileRef *tile_map;   // [map_cap] tiles of the instances by step count,
+                               // descending (round r runs a prefix of it), then
+                               // entries with rounds = 0
     const uint32_t *round_off; // [rounds + 1] first work item of each round
     const BatchGlobal *gl;
     uint32_t map_cap;          // entries allocated for tile_map (>= 1)
@@ -88,42 +92,27 @@ __device__ inline StageArgs<T> batch_stage_args(const BatchPtrs<T> &p, uint32_t 
     const double rem = in.tf - t_n;
     const double h = in.dt < rem ? in.dt : rem;
     StageArgs<T> a = in.geo;
+    // every field read before the stage picks among them (selects, not
+    // branches, so that the instance's fields are one round of loads)
+    T *const v = in.v, *const ba = in.a, *const bb = in.b;
+    const int tube = in.tube;
+    // stage 0: V -> A (Euler); RK3 stage 1: (3 V + (A + h L(A))) / 4 -> B;
+    // last stage: (V + 2 (B + h L(B))) / 3 -> V (RK3) or (V + (A + h L(A))) / 2
+    // -> V (RK2), with the tube minimum
+    const bool first = stage == 0;
+    const bool mid = stage == 1 && order == 3;
+    const bool last = !first && !mid;
     a.dt = T(h);
     a.v0 = in.v0;
-    a.tube = 0;
     a.vi = in.vi;
-    if (stage == 0) {
-        a.vs = in.v;
-        a.vb = nullptr;
-        a.out = in.a;
-        a.combine = kEuler;
-    } else if (stage == 1 && order == 3) {
-        a.vs = in.a;
-        a.vb = in.v;
-        a.out = in.b;
-        a.combine = kBlend;
-        a.wb = T(3);
-        a.w2 = T(1);
-        a.den = T(4);
-    } else if (order == 2) {
-        a.vs = in.a;
-        a.vb = in.v;
-        a.out = in.v;
-        a.combine = kBlend;
-        a.wb = T(1);
-        a.w2 = T(1);
-        a.den = T(2);
-        a.tube = in.tube;
-    } else {
-        a.vs = in.b;
-        a.vb = in.v;
-        a.out = in.v;
-        a.combine = kBlend;
-        a.wb = T(1);
-        a.w2 = T(2);
-        a.den = T(3);
-        a.tube = in.tube;
-    }
+    a.vs = first ? v : (mid || order == 2 ? ba : bb);
+    a.vb = first ? nullptr : v;
+    a.out = first ? ba : (mid ? bb : v);
+    a.combine = first ? kEuler : kBlend;
+    a.wb = mid ? T(3) : T(1);
+    a.w2 = (last && order == 3) ? T(2) : T(1);
+    a.den = mid ? T(4) : (order == 2 ? T(2) : T(3));
+    a.tube = last ? tube : 0;
     *h_out = h;
     *tn_out = t_n;
     return a;
@@ -145,23 +134,29 @@ __device__ inline void batch_item(const BatchPtrs<T> &p, uint32_t local, uint32_
 // kernel keeps the register footprint of the plain stage kernel (the loops of
 // the strided form keep about twice the VGPRs live, halving occupancy);
 // workgroups beyond the round's tiles return at once.
+// Round r is stage `stage` (r % order) of RK step `step` (r / order), both
+// passed in by the host with r, so the kernel forms no quotient.
 template <typename T, int D, int SCH, int DYN, bool FLAT>
-__global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r, uint32_t order)
+__global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r, uint32_t order,
+                                                   uint32_t stage, uint32_t step)
 {
     // r < the batch's round count: rounds are launched for exactly the batch's
     // rounds (a replayed graph was captured for the same round count)
     const uint32_t b = blockIdx.x;
-    // the map entry is loaded beside the round bounds rather than after them
-    // (clamped into the map; used only by a workgroup that has a tile)
-    const TileRef t = p.tile_map[b < p.map_cap ? b : p.map_cap - 1u];
-    const uint32_t begin = p.round_off[r], end = p.round_off[r + 1];
-    // the RK order is the launch's, so stage and step need no division here
-    const uint32_t stage = order == 3 ? r % 3u : (order == 2 ? r & 1u : 0u);
-    const uint32_t step = order == 3 ? r / 3u : (order == 2 ? r >> 1 : r);
     if (FLAT) {
-        if (b >= end - begin) return;
-        const uint32_t inst = __builtin_amdgcn_readfirstlane(t.inst);
-        const uint32_t tile = __builtin_amdgcn_readfirstlane(t.tile);
+        // Workgroup b takes map entry b, whose instance runs in this round
+        // when r < rounds (the round's tiles are a prefix of the map): one
+        // scalar load (constant address space: the map does not change
+        // during a launch) before the instance's own tables, instead of the
+        // round bounds and then the entry.
+        // (the entry is one 16-byte load, made before any branch, so that
+        // the kernel arguments and then the entry are each one round of loads)
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const uint32_t cap = p.map_cap;
+        const u32x4 e = *(const __attribute__((address_space(4))) u32x4 *)(p.tile_map +
+                                                                          (b < cap ? b : cap - 1u));
+        const uint32_t inst = e.x, tile = e.y;
+        if (b >= cap || r >= e.z) return;
         double h, t_n;
         const StageArgs<T> a = batch_stage_args(p, inst, order, stage, step, &h, &t_n);
         const uint32_t node = tile * 256u + threadIdx.x;
@@ -171,6 +166,7 @@ __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r, u
             p.ctl[inst].t[(step + 1) & 1u] = t_n + h;
         return;
     }
+    const uint32_t begin = p.round_off[r], end = p.round_off[r + 1];
     for (uint32_t k = begin + blockIdx.x; k < end; k += gridDim.x) {
         uint32_t inst, tile;
         batch_item(p, k - begin, &inst, &tile);
@@ -207,10 +203,10 @@ hipError_t batch_launch_one(const BatchPtrs<T> &p, uint32_t rounds, const BatchS
     for (uint32_t r = 0; r < rounds; ++r) {
         if (sh.workgroups)
             hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, false>), dim3(sh.workgroups),
-                               dim3(256), 0, s, p, r, order);
+                               dim3(256), 0, s, p, r, order, r % order, r / order);
         else
             hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, true>), dim3(sh.round_grid[r]),
-                               dim3(256), 0, s, p, r, order);
+                               dim3(256), 0, s, p, r, order, r % order, r / order);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
