@@ -34,6 +34,7 @@ struct hj_batch_s {
     uint32_t tile_nodes = 256;
     uint32_t workgroups = 0;   // 0: flat launches (one workgroup per 256-node tile)
     bool use_graph = true;
+    bool off32 = true;         // the current batch's arrays are all under 4 GiB
 
     // device tables and their capacities
     uint32_t cap_inst = 0, cap_rounds = 0, cap_tiles = 0;
@@ -60,6 +61,7 @@ struct hj_batch_s {
         hipGraphExec_t exec = nullptr;
         int nd = -1, space = -1, dyn = -1, prec = -1, order = -1;
         uint32_t wg = 0, rounds = 0;
+        bool off32 = true;
         std::vector<uint32_t> grid;  // flat: workgroups of each round
         uint64_t used = 0;           // last use (LRU)
     };
@@ -196,7 +198,7 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, int o
     for (uint32_t r = 0; flat && r < rounds; ++r)
         grid[r] = b->h_round_off[r + 1] - b->h_round_off[r];
     if (!b->use_graph) {
-        const BatchShape sh{b->workgroups, grid.data(), uint32_t(order)};
+        const BatchShape sh{b->workgroups, grid.data(), uint32_t(order), b->off32};
         hipError_t e = launch_any(b, nd, space, dyn, prec, rounds, sh, s);
         if (e != hipSuccess) return hip_fail(e, "batch launch");
         return HJ_OK;
@@ -204,7 +206,8 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, int o
     hj_batch_s::Graph *hit = nullptr;
     for (auto &g : b->graphs) {
         if (g.nd != nd || g.space != space || g.dyn != dyn || g.prec != prec ||
-            g.order != order || g.wg != b->workgroups || g.rounds != rounds)
+            g.order != order || g.wg != b->workgroups || g.rounds != rounds ||
+            g.off32 != b->off32)
             continue;
         bool fits = true;
         for (uint32_t r = 0; flat && r < rounds && fits; ++r) fits = grid[r] <= g.grid[r];
@@ -222,6 +225,7 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, int o
         g.prec = prec;
         g.wg = b->workgroups;
         g.rounds = rounds;
+        g.off32 = b->off32;
         g.grid.resize(grid.size());
         for (size_t r = 0; r < grid.size(); ++r) g.grid[r] = grid_capacity(grid[r]);
         if (!b->capture_stream)
@@ -230,7 +234,7 @@ hj_status run(hj_batch_t b, int nd, int space, int dyn, hj_precision prec, int o
         hipGraph_t graph = nullptr;
         HJ_HIP(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal),
                "begin capture");
-        const BatchShape sh{b->workgroups, g.grid.data(), uint32_t(order)};
+        const BatchShape sh{b->workgroups, g.grid.data(), uint32_t(order), b->off32};
         hipError_t e = launch_any(b, nd, space, dyn, prec, rounds, sh, b->capture_stream);
         hipError_t e2 = hipStreamEndCapture(b->capture_stream, &graph);
         if (e != hipSuccess) {
@@ -462,6 +466,10 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
         max_n = std::max(max_n, steps[i]);
     }
     const uint32_t order = uint32_t(g0->order);
+    b->off32 = true;
+    for (int i = 0; i < n; ++i)
+        b->off32 = b->off32 && (g0->prec == HJ_FP64 ? fits_off32<double>(uint64_t(gs[i]->total))
+                                                   : fits_off32<float>(uint64_t(gs[i]->total)));
     const uint64_t rounds64 = uint64_t(order) * max_n;
     if (rounds64 >= (uint64_t(1) << 31)) return fail(HJ_E_ARG, "too many steps");
     const uint32_t rounds = uint32_t(rounds64);

@@ -136,7 +136,7 @@ __device__ inline void batch_item(const BatchPtrs<T> &p, uint32_t local, uint32_
 // workgroups beyond the round's tiles return at once.
 // Round r is stage `stage` (r % order) of RK step `step` (r / order), both
 // passed in by the host with r, so the kernel forms no quotient.
-template <typename T, int D, int SCH, int DYN, bool FLAT>
+template <typename T, int D, int SCH, int DYN, bool FLAT, bool OFF32>
 __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r, uint32_t order,
                                                    uint32_t stage, uint32_t step)
 {
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r, u
         double h, t_n;
         const StageArgs<T> a = batch_stage_args(p, inst, order, stage, step, &h, &t_n);
         const uint32_t node = tile * 256u + threadIdx.x;
-        if (node < a.total) stage_node<T, D, SCH, DYN>(a, node);
+        if (node < a.total) stage_node<T, D, SCH, DYN, OFF32>(a, node);
         // the other slot: read by no tile of this step
         if (stage == order - 1 && tile == 0 && threadIdx.x == 0)
             p.ctl[inst].t[(step + 1) & 1u] = t_n + h;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void batch_round(BatchPtrs<T> p, uint32_t r, u
         const uint32_t first = tile * tn;
         const uint32_t last = first + tn < a.total ? first + tn : a.total;
         for (uint32_t node = first + threadIdx.x; node < last; node += 256)
-            stage_node<T, D, SCH, DYN>(a, node);
+            stage_node<T, D, SCH, DYN, OFF32>(a, node);
         if (stage == order - 1 && tile == 0 && threadIdx.x == 0)
             p.ctl[inst].t[(step + 1) & 1u] = t_n + h;
     }
@@ -189,6 +189,7 @@ struct BatchShape {
     uint32_t workgroups;
     const uint32_t *round_grid;  // host array [rounds], flat form only
     uint32_t order;              // RK order of the batch (1, 2 or 3)
+    bool off32;                  // every instance's arrays under 4 GiB (fits_off32)
 };
 
 // The init kernel and rounds [0, rounds) of the round kernel, back to back.
@@ -201,12 +202,22 @@ hipError_t batch_launch_one(const BatchPtrs<T> &p, uint32_t rounds, const BatchS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (uint32_t r = 0; r < rounds; ++r) {
-        if (sh.workgroups)
-            hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, false>), dim3(sh.workgroups),
-                               dim3(256), 0, s, p, r, order, r % order, r / order);
-        else
-            hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, true>), dim3(sh.round_grid[r]),
-                               dim3(256), 0, s, p, r, order, r % order, r / order);
+        const uint32_t st = r % order, sp = r / order;
+        if (sh.workgroups) {
+            if (sh.off32)
+                hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, false, true>),
+                                   dim3(sh.workgroups), dim3(256), 0, s, p, r, order, st, sp);
+            else
+                hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, false, false>),
+                                   dim3(sh.workgroups), dim3(256), 0, s, p, r, order, st, sp);
+        } else {
+            if (sh.off32)
+                hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, true, true>),
+                                   dim3(sh.round_grid[r]), dim3(256), 0, s, p, r, order, st, sp);
+            else
+                hipLaunchKernelGGL((batch_round<T, D, SCH, DYN, true, false>),
+                                   dim3(sh.round_grid[r]), dim3(256), 0, s, p, r, order, st, sp);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

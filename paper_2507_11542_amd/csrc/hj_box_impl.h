@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void box_partial(const StageArgs<T> a, T *part
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             T pm, pp;
-            axis_derivs<T, SCH>(global_ptr(a.vs), node, ii[d], int(a.n[d]), a.stride[d],
+            axis_derivs<T, SCH>(Arr<T, false>{global_ptr(a.vs)}, node, ii[d], int(a.n[d]), a.stride[d],
                                 (a.periodic >> d) & 1u, a.dx[d], a.inv_dx[d], a.inv_2dx[d],
                                 a.inv_3dx[d], pm, pp, center, d == D - 1);
             const T l = pm < pp ? pm : pp, h = pm < pp ? pp : pm;

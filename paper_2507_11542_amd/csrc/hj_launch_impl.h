@@ -10,7 +10,12 @@ template <typename T, int D, int SCH, int DYN>
 hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
 {
     const uint32_t blocks = (a.total + 255u) / 256u;
-    hipLaunchKernelGGL((stage_kernel<T, D, SCH, DYN>), dim3(blocks), dim3(256), 0, s, a);
+    if (fits_off32<T>(a.total))
+        hipLaunchKernelGGL((stage_kernel<T, D, SCH, DYN, true>), dim3(blocks), dim3(256), 0, s,
+                           a);
+    else
+        hipLaunchKernelGGL((stage_kernel<T, D, SCH, DYN, false>), dim3(blocks), dim3(256), 0, s,
+                           a);
     return hipGetLastError();
 }
 
