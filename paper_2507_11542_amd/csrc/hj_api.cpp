@@ -168,6 +168,7 @@ StageArgs<T> base_args(hj_grid_t g)
     }
     a.total = uint32_t(g->total);
     a.periodic = g->pmask;
+    a.addr64 = g->addr64 ? 1u : 0u;
     for (int k = 0; k < 8; ++k) a.prm[k] = T(g->prm[k]);
     a.diss = g->diss;
     a.box = (const T *)g->box_dev;
@@ -456,6 +457,9 @@ hj_status hj_grid_create(int ndim, const int64_t *N, const double *lo, const dou
             t64[g->tab_off[d] + 2 * N[d] + k] = std::sin(x);
         }
     hj_status s = HJ_OK;
+    // test switch: the 64-bit-addressing form of the stage kernels whatever
+    // the grid's size (the form grids of 4 GiB arrays and more take)
+    g->addr64 = std::getenv("HJ_ADDR64") != nullptr;
     hipError_t e = hipGetDevice(&g->device);
     if (e != hipSuccess) s = hip_fail(e, "hipGetDevice");
     if (s == HJ_OK) s = dev_alloc((void **)&g->tab64, sizeof(double) * off, "coordinate table");

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -35,6 +36,7 @@ struct hj_batch_s {
     uint32_t workgroups = 0;   // 0: flat launches (one workgroup per 256-node tile)
     bool use_graph = true;
     bool off32 = true;         // the current batch's arrays are all under 4 GiB
+    bool addr64 = false;       // HJ_ADDR64 set at creation: 64-bit addressing (test switch)
 
     // device tables and their capacities
     uint32_t cap_inst = 0, cap_rounds = 0, cap_tiles = 0;
@@ -312,6 +314,7 @@ hj_status hj_batch_create(hj_batch_t *out)
     hj_batch_s *b = new (std::nothrow) hj_batch_s();
     if (!b) return fail(HJ_E_OOM, "host allocation of the batch handle");
     hj_status s = HJ_OK;
+    b->addr64 = std::getenv("HJ_ADDR64") != nullptr;
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) s = hip_fail(e, "hipGetDevice");
     if (s == HJ_OK) s = dev_alloc((void **)&b->gl, sizeof(BatchGlobal), "batch globals");
@@ -466,7 +469,7 @@ hj_status batch_run(hj_batch_t b, int n, const hj_grid_t *gs, const void *const 
         max_n = std::max(max_n, steps[i]);
     }
     const uint32_t order = uint32_t(g0->order);
-    b->off32 = true;
+    b->off32 = !b->addr64;
     for (int i = 0; i < n; ++i)
         b->off32 = b->off32 && (g0->prec == HJ_FP64 ? fits_off32<double>(uint64_t(gs[i]->total))
                                                    : fits_off32<float>(uint64_t(gs[i]->total)));

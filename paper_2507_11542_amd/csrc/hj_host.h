@@ -22,6 +22,7 @@ struct hj_grid_s {
     uint32_t stride[hj::kMaxDim] = {0, 0, 0, 0};
     uint32_t tab_off[hj::kMaxDim] = {0, 0, 0, 0};
     int device = 0;
+    bool addr64 = false;  // HJ_ADDR64 set when the grid was created (test switch)
 
     int dyn = -1;
     double prm[8] = {0, 0, 0, 0, 0, 0, 0, 0};

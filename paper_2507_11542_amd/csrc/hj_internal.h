@@ -48,6 +48,7 @@ struct StageArgs {
     uint32_t nshift[kMaxDim];
     uint32_t total;
     uint32_t periodic;  // bit d: axis d periodic
+    uint32_t addr64;    // host side: launch the 64-bit-addressing form whatever the size
     T dx[kMaxDim];
     T inv_dx[kMaxDim];   // 1/dx (FP64 on the host, then rounded to T)
     T inv_2dx[kMaxDim];  // 1/(2 dx)

@@ -10,7 +10,7 @@ template <typename T, int D, int SCH, int DYN>
 hipError_t launch_one(const StageArgs<T> &a, hipStream_t s)
 {
     const uint32_t blocks = (a.total + 255u) / 256u;
-    if (fits_off32<T>(a.total))
+    if (!a.addr64 && fits_off32<T>(a.total))
         hipLaunchKernelGGL((stage_kernel<T, D, SCH, DYN, true>), dim3(blocks), dim3(256), 0, s,
                            a);
     else

@@ -362,3 +362,46 @@ def test_full_size_dubins4d_fp32_side_by_side():
     assert band.sum() > 50
     assert err[band].max() <= 1e-4
     assert err.max() <= 5e-3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_64bit_addressing_form_equals_32bit(monkeypatch, prec):
+    """Grids whose arrays reach 4 GiB take the stage kernels' 64-bit-addressing
+    form; smaller ones the 32-bit-offset form.  HJ_ADDR64 (read when a grid or
+    batch is created) forces the former on small grids: the two forms give
+    the same results bit for bit (plain solves of WENO5, ENO2 with the
+    shuffled fastest axis in FP64, and a batch)."""
+    import torch
+
+    from gpu_util import gpu_solve, to_dev
+    from paper_2507_11542_amd import hj
+
+    probs = [inputs.rel_dubins_3d(n=(23, 29, 18), tf=0.2),
+             inputs.double_integrator_2d(n=67),
+             inputs.dubins4d(n=(11, 13, 9, 10), tf=0.1)]
+
+    def run():
+        outs = [gpu_solve(p, prec) for p in probs]
+        grids = [hj.Grid.from_problem(p, prec) for p in probs[:1] * 2]
+        v0s = [to_dev(probs[0].v0(), prec) for _ in grids]
+        bo = [torch.empty_like(v) for v in v0s]
+        b = hj.Batch()
+        st = torch.cuda.current_stream()
+        try:
+            b.solve(grids, v0s, bo, [probs[0].t0] * 2, [probs[0].tf] * 2,
+                    [probs[0].mode] * 2, st)
+            b.wait(2, st)
+            torch.cuda.synchronize()
+        finally:
+            b.close()
+            for g in grids:
+                g.close()
+        return outs + [x.cpu().numpy() for x in bo]
+
+    print("case addressing forms", prec, flush=True)
+    monkeypatch.delenv("HJ_ADDR64", raising=False)
+    a = run()
+    monkeypatch.setenv("HJ_ADDR64", "1")
+    b = run()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
