@@ -28,6 +28,7 @@ MUTATIONS = {
     "weno_right_weights_order": ("w[4], w[3], w[2], w[1], w[0], r.rc, r.rb, r.ra",
                                  "w[4], w[3], w[2], w[1], w[0], r.ra, r.rb, r.rc"),
     "weno_right_stencil_order": ("*pp = weno_right(&d1[1]);", "*pp = weno_left(&d1[1]);"),
+    "weno_eps_scale": ("double eps = 1e-6 * mx + 1e-99;", "double eps = 1e-4 * mx + 1e-99;"),
     "lf_dissipation_sign": ("diss += a * ((pp[d] - pm[d]) / 2.0);",
                             "diss -= a * ((pp[d] - pm[d]) / 2.0);"),
     "rhs_sign": ("    return -hhat;\n}", "    return hhat;\n}"),
@@ -83,7 +84,7 @@ MUTATIONS = {
 }
 
 PIN_FILES = ("test_oracle_pins.py", "test_oracle_rockets_tubes.py", "test_oracle_shapes.py",
-             "test_oracle_dissipation.py")
+             "test_oracle_dissipation.py", "test_oracle_exact_derivs.py")
 
 # The pin file that targets each group of mutations runs first (every pin
 # file still runs until one test fails, so this only saves time).
@@ -93,7 +94,9 @@ FIRST_FILE = (("box_", "test_oracle_dissipation.py"), ("glf_", "test_oracle_diss
               ("rockets_", "test_oracle_rockets_tubes.py"), ("vi_", "test_oracle_rockets_tubes.py"),
               ("tube_out", "test_oracle_rockets_tubes.py"),
               ("ellipsoid", "test_oracle_shapes.py"), ("sphere", "test_oracle_shapes.py"),
-              ("union", "test_oracle_shapes.py"), ("subtract", "test_oracle_shapes.py"))
+              ("union", "test_oracle_shapes.py"), ("subtract", "test_oracle_shapes.py"),
+              ("weno_", "test_oracle_exact_derivs.py"), ("eno", "test_oracle_exact_derivs.py"),
+              ("upwind_", "test_oracle_exact_derivs.py"))
 
 
 def _pin_order(name):
