@@ -138,15 +138,34 @@ template <typename T>
 __device__ inline WenoR<T> weno_window(T w0, T w1, T w2, T w3, T w4)
 {
     constexpr T c13_12 = T(13.0 / 12.0);
-    const T ea = (w0 + w2) - T(2) * w1;
-    const T eb = (w1 + w3) - T(2) * w2;
-    const T ec = (w2 + w4) - T(2) * w3;
-    const T fa = (w0 + T(3) * w2) - T(4) * w1;
-    const T fb = w1 - w3;
-    const T fc = (T(3) * w2 + w4) - T(4) * w3;
-    const T sa = c13_12 * ea * ea + T(0.25) * fa * fa;
-    const T sb = c13_12 * eb * eb + T(0.25) * fb * fb;
-    const T sc = c13_12 * ec * ec + T(0.25) * fc * fc;
+    T sa, sb, sc;
+    if constexpr (sizeof(T) == 8) {
+        // The products by 2, 4 and 1/4 are exact, so a fused multiply-add
+        // that takes one of them rounds once, where the written product and
+        // sum round once (the sum) too: the same value, one instruction
+        // fewer.  For the 1/4 the product fa fa is rounded first, which
+        // differs from rounding (fa/4) fa only below the normal range, and
+        // there by less than the eps floor resolves in S + eps.
+        const double ea = __builtin_fma(-2.0, w1, w0 + w2);
+        const double eb = __builtin_fma(-2.0, w2, w1 + w3);
+        const double ec = __builtin_fma(-2.0, w3, w2 + w4);
+        const double fa = __builtin_fma(-4.0, w1, w0 + 3.0 * w2);
+        const double fb = w1 - w3;
+        const double fc = __builtin_fma(-4.0, w3, 3.0 * w2 + w4);
+        sa = __builtin_fma(0.25, fa * fa, c13_12 * ea * ea);
+        sb = __builtin_fma(0.25, fb * fb, c13_12 * eb * eb);
+        sc = __builtin_fma(0.25, fc * fc, c13_12 * ec * ec);
+    } else {
+        const T ea = (w0 + w2) - T(2) * w1;
+        const T eb = (w1 + w3) - T(2) * w2;
+        const T ec = (w2 + w4) - T(2) * w3;
+        const T fa = (w0 + T(3) * w2) - T(4) * w1;
+        const T fb = w1 - w3;
+        const T fc = (T(3) * w2 + w4) - T(4) * w3;
+        sa = c13_12 * ea * ea + T(0.25) * fa * fa;
+        sb = c13_12 * eb * eb + T(0.25) * fb * fb;
+        sc = c13_12 * ec * ec + T(0.25) * fc * fc;
+    }
     // max_k w_k^2 as (max_k |w_k|)^2: rounding is monotone in |w|, so the
     // rounded square of the largest magnitude is the largest rounded square
     const T m = fmax(fmax(fmax(fmax(fabs(w0), fabs(w1)), fabs(w2)), fabs(w3)), fabs(w4));
@@ -601,13 +620,19 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
                             (a.periodic >> d) & 1u, a.dx[d], a.inv_dx[d], a.inv_2dx[d],
                             a.inv_3dx[d], pm[d], pp[d], center, d == D - 1);
     }
+    // Twice p-bar and twice the dissipation: H is positively homogeneous of
+    // degree one in p (sums, products by coefficients, absolute values, the
+    // square root of a sum of squares), and a factor 2 commutes with every
+    // rounding, so H(pp + pm) - sum alpha (pp - pm) is exactly twice the
+    // Lax-Friedrichs Hhat and one product by -1/2 below replaces the 2 D
+    // halvings (outside the normal range aside).
     T pbar[D];
     T diss = T(0);
     if (a.diss == kLF) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            pbar[d] = (pp[d] + pm[d]) * T(0.5);
-            diss += a.alpha[d] * ((pp[d] - pm[d]) * T(0.5));
+            pbar[d] = pp[d] + pm[d];
+            diss += a.alpha[d] * (pp[d] - pm[d]);
         }
     } else {
         T lo[D], hi[D];
@@ -623,11 +648,11 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            pbar[d] = (pp[d] + pm[d]) * T(0.5);
-            diss += box_bound<T, D, DYN>(a, ii, d, lo, hi) * ((pp[d] - pm[d]) * T(0.5));
+            pbar[d] = pp[d] + pm[d];
+            diss += box_bound<T, D, DYN>(a, ii, d, lo, hi) * (pp[d] - pm[d]);
         }
     }
-    T l = -(hamiltonian<T, D, DYN>(a, ii, pbar) - diss);
+    T l = (hamiltonian<T, D, DYN>(a, ii, pbar) - diss) * T(-0.5);
     if (a.vi && l > T(0)) l = T(0);
 
     T val;
