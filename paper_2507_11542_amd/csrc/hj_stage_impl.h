@@ -357,10 +357,12 @@ __device__ inline void axis_derivs(const Arr<T, O> &v, uint32_t node, int i, int
     T s[2 * W + 1];
     const bool interior = i >= W && i < n - W;
     if (fastest) {
+        // the last axis is the contiguous one (C order): stride 1, which
+        // spares the index arithmetic its integer multiplies
         if constexpr (ShuffleFastest<T, SCH>::value)
             line_stencil_shuffle<T, W>(v, node, i, n, periodic, s);
         else
-            line_stencil_select<T, W>(v, node, i, n, stride, periodic, s);
+            line_stencil_select<T, W>(v, node, i, n, 1u, periodic, s);
     } else if (interior) {
 #pragma unroll
         for (int k = 0; k <= 2 * W; ++k) s[k] = v[node + (k - W) * int(stride)];
