@@ -66,17 +66,20 @@ __device__ inline gmem<T> *elem_at(gmem<T> *p, uint32_t i)
     }
 }
 
-// node index -> axis indices (C order) with the host's division magic
+// node index -> axis indices (C order) with the host's division magic; the
+// quotient left after the last D-1 axes is the first axis's index, since
+// node < n[0] n[1] ... n[D-1]
 template <typename T, int D>
 __device__ inline void node_indices(const StageArgs<T> &a, uint32_t node, int *ii)
 {
     uint32_t r = node;
 #pragma unroll
-    for (int d = D - 1; d >= 0; --d) {
+    for (int d = D - 1; d >= 1; --d) {
         const uint32_t q = uint32_t((uint64_t(r) * a.nmul[d]) >> a.nshift[d]);
         ii[d] = int(r - q * a.n[d]);
         r = q;
     }
+    ii[0] = int(r);
 }
 
 template <int SCH>
@@ -236,12 +239,14 @@ template <typename T, int W, bool O>
 __device__ inline void line_stencil_select(const Arr<T, O> &v, uint32_t node, int i, int n,
                                            uint32_t stride, bool periodic, T *s)
 {
+    // 0 <= i < n, so an index left of the node can leave the line only at
+    // its first end and one right of it only at its last: one test each
     const uint32_t base = node - uint32_t(i) * stride;
     if (periodic) {
 #pragma unroll
         for (int k = 0; k <= 2 * W; ++k) {
             const int j = i - W + k;
-            const int jw = j < 0 ? j + n : (j >= n ? j - n : j);
+            const int jw = k < W ? (j < 0 ? j + n : j) : (k > W ? (j >= n ? j - n : j) : i);
             s[k] = v[base + uint32_t(jw) * stride];
         }
         return;
@@ -249,7 +254,7 @@ __device__ inline void line_stencil_select(const Arr<T, O> &v, uint32_t node, in
 #pragma unroll
     for (int k = 0; k <= 2 * W; ++k) {
         const int j = i - W + k;
-        const int jc = j < 0 ? 0 : (j >= n ? n - 1 : j);
+        const int jc = k < W ? (j < 0 ? 0 : j) : (k > W ? (j >= n ? n - 1 : j) : i);
         s[k] = v[base + uint32_t(jc) * stride];
     }
     const T e0 = v[base], e1 = v[base + stride];
@@ -439,7 +444,9 @@ __device__ inline void axis_derivs(const Arr<T, O> &v, uint32_t node, int i, int
     }
 }
 
-// H(x, p) of the compiled dynamics (sign convention V_t + H = 0).
+// H(x, p) of the compiled dynamics (sign convention V_t + H = 0).  The
+// coordinate tables (x, cos x, sin x per node of each axis) are read with
+// 32-bit byte offsets: they hold 3 entries per grid line position.
 template <typename T, int D, int DYN>
 __device__ inline T hamiltonian(const StageArgs<T> &a, const int *ii, const T *p)
 {
@@ -454,32 +461,32 @@ __device__ inline T hamiltonian(const StageArgs<T> &a, const int *ii, const T *p
         for (int d = 0; d < D; ++d) s += p[d] * p[d];
         return a.prm[0] * sqrt(s);
     } else if constexpr (DYN == kDoubleIntegrator) {
-        const T x2 = global_ptr(a.tab)[a.tab_off[1] + ii[1]];
+        const T x2 = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[1] + ii[1]];
         return -p[0] * x2 + a.prm[0] * fabs(p[1]);
     } else if constexpr (DYN == kRelDubins) {
         const T ve = a.prm[0], vp = a.prm[1], we = a.prm[2], wp = a.prm[3];
-        const T x = global_ptr(a.tab)[a.tab_off[0] + ii[0]];
-        const T y = global_ptr(a.tab)[a.tab_off[1] + ii[1]];
-        const T c = global_ptr(a.tab)[a.tab_off[2] + a.n[2] + ii[2]];
-        const T s = global_ptr(a.tab)[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+        const T x = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[0] + ii[0]];
+        const T y = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[1] + ii[1]];
+        const T c = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[2] + a.n[2] + ii[2]];
+        const T s = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[2] + 2 * a.n[2] + ii[2]];
         return -p[0] * (-ve + vp * c) - p[1] * (vp * s) - we * fabs(p[0] * y - p[1] * x - p[2]) +
                wp * fabs(p[2]);
     } else if constexpr (DYN == kRockets) {
         // (x, z, th): p.f = p1 a cos th + p2 (a sin th + a - g) + ue (p1 x - p3)
         // + up (p2 x + p3), evader ue maximising, pursuer up minimising
         const T am = a.prm[0], grav = a.prm[1], um = a.prm[2];
-        const T x = global_ptr(a.tab)[a.tab_off[0] + ii[0]];
-        const T c = global_ptr(a.tab)[a.tab_off[2] + a.n[2] + ii[2]];
-        const T s = global_ptr(a.tab)[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+        const T x = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[0] + ii[0]];
+        const T c = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[2] + a.n[2] + ii[2]];
+        const T s = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[2] + 2 * a.n[2] + ii[2]];
         const T drift1 = am * c;
         const T drift2 = am * s + am - grav;
         return -p[0] * drift1 - p[1] * drift2 - um * fabs(p[0] * x - p[2]) +
                um * fabs(p[1] * x + p[2]);
     } else {
         const T wm = a.prm[0], am = a.prm[1];
-        const T c = global_ptr(a.tab)[a.tab_off[2] + a.n[2] + ii[2]];
-        const T s = global_ptr(a.tab)[a.tab_off[2] + 2 * a.n[2] + ii[2]];
-        const T v = global_ptr(a.tab)[a.tab_off[3] + ii[3]];
+        const T c = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[2] + a.n[2] + ii[2]];
+        const T s = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[2] + 2 * a.n[2] + ii[2]];
+        const T v = Arr<T, true>{global_ptr(a.tab)}[a.tab_off[3] + ii[3]];
         return -p[0] * (v * c) - p[1] * (v * s) + wm * fabs(p[2]) + am * fabs(p[3]);
     }
 }
@@ -525,7 +532,7 @@ template <typename T, int D, int DYN>
 __device__ inline T box_bound(const StageArgs<T> &a, const int *ii, int d, const T *lo,
                               const T *hi)
 {
-    const gmem<T> *tab = global_ptr(a.tab);
+    const Arr<T, true> tab{global_ptr(a.tab)};
     if constexpr (DYN == kBall) {
         const T big = fabs(lo[d]) > fabs(hi[d]) ? fabs(lo[d]) : fabs(hi[d]);
         T rest = T(0);
