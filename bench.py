@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 SPREAD_BAR_FACTOR = 4.0
 
 MEASURED_TRAFFIC = {
-    "fp64": {"src_hash": "f79cc5dd253634e2", "fetch_kib": 9832.4, "write_kib": 8049.2,
+    "fp64": {"src_hash": "307d4acd466a88ec", "fetch_kib": 9827.6, "write_kib": 8049.2,
              "fetch_scale": 2.0, "write_scale": 1.0},
-    "fp32": {"src_hash": "f79cc5dd253634e2", "fetch_kib": 4940.6, "write_kib": 4024.6,
+    "fp32": {"src_hash": "307d4acd466a88ec", "fetch_kib": 4934.1, "write_kib": 4024.6,
              "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
