@@ -137,8 +137,10 @@ __device__ inline T wrecip(T x)
         return __builtin_amdgcn_rcpf(x);
 }
 
+// m: max_k |w_k|, the caller's (the two windows of a node share four of
+// their five differences, so they share most of the maximum)
 template <typename T>
-__device__ inline WenoR<T> weno_window(T w0, T w1, T w2, T w3, T w4)
+__device__ inline WenoR<T> weno_window(T w0, T w1, T w2, T w3, T w4, T m)
 {
     constexpr T c13_12 = T(13.0 / 12.0);
     T sa, sb, sc;
@@ -171,7 +173,6 @@ __device__ inline WenoR<T> weno_window(T w0, T w1, T w2, T w3, T w4)
     }
     // max_k w_k^2 as (max_k |w_k|)^2: rounding is monotone in |w|, so the
     // rounded square of the largest magnitude is the largest rounded square
-    const T m = fmax(fmax(fmax(fmax(fabs(w0), fabs(w1)), fabs(w2)), fabs(w3)), fabs(w4));
     const T eps = T(1e-6) * (m * m) + (sizeof(T) == 8 ? T(1e-99) : T(1e-18));
     WenoR<T> r;
     r.ra = wrecip((sa + eps) * (sa + eps));
@@ -433,9 +434,11 @@ __device__ inline void axis_derivs(const Arr<T, O> &v, uint32_t node, int i, int
         for (int k = 0; k < 6; ++k)
             d1[k] = undivided ? s[k + 1] - s[k] : (s[k + 1] - s[k]) * inv_dx;
         // p-: left-biased on the window d1[0..4]; p+: right-biased on d1[1..5]
-        const WenoR<T> rl = weno_window(d1[0], d1[1], d1[2], d1[3], d1[4]);
+        // the largest |difference| of each window (max is exact in any order)
+        const T mc = fmax(fmax(fabs(d1[1]), fabs(d1[2])), fmax(fabs(d1[3]), fabs(d1[4])));
+        const WenoR<T> rl = weno_window(d1[0], d1[1], d1[2], d1[3], d1[4], fmax(fabs(d1[0]), mc));
         pm = weno_blend(d1[0], d1[1], d1[2], d1[3], d1[4], rl.ra, rl.rb, rl.rc);
-        const WenoR<T> rr = weno_window(d1[1], d1[2], d1[3], d1[4], d1[5]);
+        const WenoR<T> rr = weno_window(d1[1], d1[2], d1[3], d1[4], d1[5], fmax(mc, fabs(d1[5])));
         pp = weno_blend(d1[5], d1[4], d1[3], d1[2], d1[1], rr.rc, rr.rb, rr.ra);
         if (undivided) {
             pm *= inv_dx;
@@ -684,17 +687,18 @@ __device__ inline void stage_node(const StageArgs<T> &a, uint32_t node)
     __builtin_nontemporal_store(val, elem_at<OFF32>(global_ptr(a.out), node));
 }
 
-// Occupancy floor of the per-node kernel: the 3-D FP64 WENO5 kernels fit 80
-// VGPRs without spilling, which gives 6 waves per SIMD instead of 5;
-// elsewhere no floor (a floor of 6 makes the 3-D ENO3 and 4-D FP64 kernels
-// spill).
+// Occupancy floor of the per-node kernel: the 3-D FP64 WENO5 kernels fit 72
+// VGPRs without spilling, which gives 7 waves per SIMD (left to itself the
+// compiler takes 74 and 6 waves); elsewhere no floor (a floor of 6 makes the
+// 3-D ENO3 and 4-D FP64 kernels spill, and 8 waves spill the 3-D FP64 WENO5
+// kernels, slower).
 template <typename T, int D, int SCH>
 struct StageWaves {
     static constexpr int value = 1;
 };
 template <>
 struct StageWaves<double, 3, kWeno5> {
-    static constexpr int value = 6;
+    static constexpr int value = 7;
 };
 
 // Tile of workgroup b out of nb.  Workgroups are dispatched to the chip's 8
