@@ -29,6 +29,14 @@ MUTATIONS = {
                                  "w[4], w[3], w[2], w[1], w[0], r.ra, r.rb, r.rc"),
     "weno_right_stencil_order": ("*pp = weno_right(&d1[1]);", "*pp = weno_left(&d1[1]);"),
     "weno_eps_scale": ("double eps = 1e-6 * mx + 1e-99;", "double eps = 1e-4 * mx + 1e-99;"),
+    "dubins4d_accel_sign": ("+ wm * fabs(p[2]) + am * fabs(p[3]);",
+                            "+ wm * fabs(p[2]) - am * fabs(p[3]);"),
+    "dubins4d_heading_swapped": ("return -p[0] * (v * g->cs[2][k]) - p[1] * (v * g->sn[2][k])",
+                                 "return -p[0] * (v * g->sn[2][k]) - p[1] * (v * g->cs[2][k])"),
+    "double_integrator_control_sign": ("return -p[0] * x2 + dy->prm[0] * fabs(p[1]);",
+                                       "return -p[0] * x2 - dy->prm[0] * fabs(p[1]);"),
+    "translation_sign": ("for (int d = 0; d < g->nd; ++d) h -= dy->prm[d] * p[d];",
+                         "for (int d = 0; d < g->nd; ++d) h += dy->prm[d] * p[d];"),
     "lf_dissipation_sign": ("diss += a * ((pp[d] - pm[d]) / 2.0);",
                             "diss -= a * ((pp[d] - pm[d]) / 2.0);"),
     "rhs_sign": ("    return -hhat;\n}", "    return hhat;\n}"),
@@ -84,7 +92,8 @@ MUTATIONS = {
 }
 
 PIN_FILES = ("test_oracle_pins.py", "test_oracle_rockets_tubes.py", "test_oracle_shapes.py",
-             "test_oracle_dissipation.py", "test_oracle_exact_derivs.py")
+             "test_oracle_dissipation.py", "test_oracle_exact_derivs.py",
+             "test_oracle_hamiltonians.py")
 
 # The pin file that targets each group of mutations runs first (every pin
 # file still runs until one test fails, so this only saves time).
