@@ -161,19 +161,24 @@ __device__ inline WenoR<T> weno_window(T w0, T w1, T w2, T w3, T w4, T m)
         sb = __builtin_fma(0.25, fb * fb, c13_12 * eb * eb);
         sc = __builtin_fma(0.25, fc * fc, c13_12 * ec * ec);
     } else {
+        // FP32: the weights depend on S + eps only through their ratios, so
+        // S and eps are both taken 12/13 times their values (S as
+        // e^2 + 3/13 f^2), one product fewer per indicator
+        constexpr T c3_13 = T(3.0 / 13.0);
         const T ea = (w0 + w2) - T(2) * w1;
         const T eb = (w1 + w3) - T(2) * w2;
         const T ec = (w2 + w4) - T(2) * w3;
         const T fa = (w0 + T(3) * w2) - T(4) * w1;
         const T fb = w1 - w3;
         const T fc = (T(3) * w2 + w4) - T(4) * w3;
-        sa = c13_12 * ea * ea + T(0.25) * fa * fa;
-        sb = c13_12 * eb * eb + T(0.25) * fb * fb;
-        sc = c13_12 * ec * ec + T(0.25) * fc * fc;
+        sa = ea * ea + c3_13 * fa * fa;
+        sb = eb * eb + c3_13 * fb * fb;
+        sc = ec * ec + c3_13 * fc * fc;
     }
     // max_k w_k^2 as (max_k |w_k|)^2: rounding is monotone in |w|, so the
     // rounded square of the largest magnitude is the largest rounded square
-    const T eps = T(1e-6) * (m * m) + (sizeof(T) == 8 ? T(1e-99) : T(1e-18));
+    const T eps = sizeof(T) == 8 ? T(1e-6) * (m * m) + T(1e-99)
+                                 : T(1e-6 * 12.0 / 13.0) * (m * m) + T(1e-18 * 12.0 / 13.0);
     WenoR<T> r;
     r.ra = wrecip((sa + eps) * (sa + eps));
     r.rb = wrecip((sb + eps) * (sb + eps));
@@ -194,11 +199,15 @@ __device__ inline T weno_blend(T v1, T v2, T v3, T v4, T v5, T r1, T r2, T r3)
     const T phi1 = v1 * c1_3 - v2 * c7_6 + v3 * c11_6;
     const T phi2 = -v2 * c1_6 + v3 * c5_6 + v4 * c1_3;
     const T phi3 = v3 * c1_3 + v4 * c5_6 - v5 * c1_6;
-    const T a1 = T(0.1) * r1, a2 = T(0.6) * r2, a3 = T(0.3) * r3;
-    if constexpr (sizeof(T) == 8)
+    if constexpr (sizeof(T) == 8) {
+        const T a1 = T(0.1) * r1, a2 = T(0.6) * r2, a3 = T(0.3) * r3;
         return div_rn_inrange(a1 * phi1 + a2 * phi2 + a3 * phi3, a1 + a2 + a3);
-    else
+    } else {
+        // FP32: the ideal weights 1/10, 6/10, 3/10 times 10 (the
+        // normalisation removes the common factor), one product fewer
+        const T a1 = r1, a2 = T(6) * r2, a3 = T(3) * r3;
         return (a1 * phi1 + a2 * phi2 + a3 * phi3) * wrecip(a1 + a2 + a3);
+    }
 }
 
 // ENO2 choice of the smaller second difference; ties go to the first (<=).
