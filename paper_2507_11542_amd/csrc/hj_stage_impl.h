@@ -191,22 +191,26 @@ __device__ inline WenoR<T> weno_window(T w0, T w1, T w2, T w3, T w4, T m)
 template <typename T>
 __device__ inline T weno_blend(T v1, T v2, T v3, T v4, T v5, T r1, T r2, T r3)
 {
-    constexpr T c1_3 = T(1.0 / 3.0);
-    constexpr T c1_6 = T(1.0 / 6.0);
-    constexpr T c5_6 = T(5.0 / 6.0);
-    constexpr T c7_6 = T(7.0 / 6.0);
-    constexpr T c11_6 = T(11.0 / 6.0);
-    const T phi1 = v1 * c1_3 - v2 * c7_6 + v3 * c11_6;
-    const T phi2 = -v2 * c1_6 + v3 * c5_6 + v4 * c1_3;
-    const T phi3 = v3 * c1_3 + v4 * c5_6 - v5 * c1_6;
     if constexpr (sizeof(T) == 8) {
+        constexpr T c1_3 = T(1.0 / 3.0);
+        constexpr T c1_6 = T(1.0 / 6.0);
+        constexpr T c5_6 = T(5.0 / 6.0);
+        constexpr T c7_6 = T(7.0 / 6.0);
+        constexpr T c11_6 = T(11.0 / 6.0);
+        const T phi1 = v1 * c1_3 - v2 * c7_6 + v3 * c11_6;
+        const T phi2 = -v2 * c1_6 + v3 * c5_6 + v4 * c1_3;
+        const T phi3 = v3 * c1_3 + v4 * c5_6 - v5 * c1_6;
         const T a1 = T(0.1) * r1, a2 = T(0.6) * r2, a3 = T(0.3) * r3;
         return div_rn_inrange(a1 * phi1 + a2 * phi2 + a3 * phi3, a1 + a2 + a3);
     } else {
-        // FP32: the ideal weights 1/10, 6/10, 3/10 times 10 (the
-        // normalisation removes the common factor), one product fewer
+        // FP32: the candidates times 6 (integer coefficients, two fused
+        // steps each; the caller's 1/dx takes the 1/6) and the ideal weights
+        // 1/10, 6/10, 3/10 times 10 (the normalisation removes the factor)
+        const T q1 = T(11) * v3 + (T(2) * v1 - T(7) * v2);
+        const T q2 = T(5) * v3 + (T(2) * v4 - v2);
+        const T q3 = T(5) * v4 + (T(2) * v3 - v5);
         const T a1 = r1, a2 = T(6) * r2, a3 = T(3) * r3;
-        return (a1 * phi1 + a2 * phi2 + a3 * phi3) * wrecip(a1 + a2 + a3);
+        return (a1 * q1 + a2 * q2 + a3 * q3) * wrecip(a1 + a2 + a3);
     }
 }
 
@@ -449,9 +453,10 @@ __device__ inline void axis_derivs(const Arr<T, O> &v, uint32_t node, int i, int
         pm = weno_blend(d1[0], d1[1], d1[2], d1[3], d1[4], rl.ra, rl.rb, rl.rc);
         const WenoR<T> rr = weno_window(d1[1], d1[2], d1[3], d1[4], d1[5], fmax(mc, fabs(d1[5])));
         pp = weno_blend(d1[5], d1[4], d1[3], d1[2], d1[1], rr.rc, rr.rb, rr.ra);
-        if (undivided) {
-            pm *= inv_dx;
-            pp *= inv_dx;
+        if (undivided) {  // 1/dx, and the 1/6 of the FP32 candidates
+            const T k = inv_dx * T(1.0 / 6.0);
+            pm *= k;
+            pp *= k;
         }
     }
 }
