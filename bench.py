@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 SPREAD_BAR_FACTOR = 4.0
 
 MEASURED_TRAFFIC = {
-    "fp64": {"src_hash": "1e458207b96c920f", "fetch_kib": 9827.3, "write_kib": 8049.2,
+    "fp64": {"src_hash": "9ac697e22dbca3da", "fetch_kib": 9827.3, "write_kib": 8049.2,
              "fetch_scale": 2.0, "write_scale": 1.0},
-    "fp32": {"src_hash": "1e458207b96c920f", "fetch_kib": 4934.1, "write_kib": 4024.6,
+    "fp32": {"src_hash": "9ac697e22dbca3da", "fetch_kib": 4930.6, "write_kib": 4024.6,
              "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
